@@ -1,0 +1,207 @@
+"""Benchmark: dump + restore of a synthetic device state on one MI355X.
+
+A step is one pass of the whole hot path over the workload: a full dump of
+every allocation into a verified image in pinned host memory (chunk digests,
+zero detection, look-back compaction, gather, D2H ring), then a restore of
+that image back into the allocations (H2D ring, scatter, verification).
+
+Default workload: the training state of a 1.3B-parameter decoder (bf16
+parameters, fp32 master weights and Adam moments, 8 GiB of bf16
+activations; 303 allocations, ~27 GB), 64 KiB chunks.
+
+Prints one JSON line. `value` = logical bytes dumped plus restored per second
+of the timed steps (GB/s, 1e9). `roofline` is the dump-mode chunk kernel
+against the HBM peak on its algorithmic bytes (read N, write D, 9 bytes of
+tables per chunk), timed by HIP events on the stream it runs on.
+`cpu_baseline` is the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "dump/restore GB/s at 1 GPU (% of HBM & host-link peak); p50/p99 ckpt latency"
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def link_baseline(torch, nbytes=4 << 30, reps=3):
+    """Pinned hipMemcpy bandwidth, D2H and H2D, measured in this run."""
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    out = {}
+    for name, fn in (("d2h", lambda: h.copy_(d, non_blocking=True)), ("h2d", lambda: d.copy_(h, non_blocking=True))):
+        best = 0.0
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = max(best, nbytes / (time.perf_counter() - t0) / 1e9)
+        out[name] = best
+    del d, h
+    return out
+
+
+def build_workload(name, torch):
+    import workloads
+    if name == "training":
+        return workloads.training_state("cuda", seed=2), 65536, "decoder-1.3B training state (303 allocations)"
+    if name == "tiny":
+        return workloads.tiny_image("cuda", seed=1), 65536, "tiny image (8 allocations, 16 MiB)"
+    if name == "hpc":
+        t, _ = workloads.hpc_state("cuda", seed=3)
+        return t, 65536, "HPC image (512 fp64/int32 allocations, 40 GB, 60% zero chunks)"
+    if name == "fragmented":
+        return workloads.fragmented_state("cuda", seed=4), 65536, "fragmented (10,000 allocations, 60 GB)"
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(table, chunk, budget_bytes):
+    """The CPU oracle (plain C, Sarwate CRC) on the first allocations of the
+    workload up to budget_bytes; device bytes are copied to the host first
+    (not timed)."""
+    import numpy as np
+    from oracle import oracle
+    import workloads
+    sample, total = [], 0
+    for i, t in table:
+        nb = t.numel() * t.element_size()
+        if total and total + nb > budget_bytes:
+            continue
+        sample.append((i, t))
+        total += nb
+        if total >= budget_bytes:
+            break
+    host = workloads.host_copy(sample)
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    rc, img = oracle.dump(host, chunk, threads=threads)
+    dt = time.perf_counter() - t0
+    assert rc == 0
+    return {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "full dump of %d of the workload's allocations (%.2f GB), %d threads, %.1f s"
+                      % (len(sample), total / 1e9, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="training", choices=["training", "tiny", "hpc", "fragmented"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--budget", type=int, default=8 << 30, help="device staging budget in bytes")
+    ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=float, default=4e9, help="bytes of the oracle sample (0 = skip)")
+    ap.add_argument("--check", action="store_true", help="verify restored bytes after each step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (each GPU's allocations form an "
+              "independent image), so --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_16631_amd import mickpt as mk
+
+    link = link_baseline(torch)
+    table, chunk, wdesc = build_workload(args.workload, torch)
+    if args.chunk:
+        chunk = args.chunk
+    torch.cuda.synchronize()
+    N = sum(t.numel() * t.element_size() for _, t in table)
+    ctx = mk.ckpt_ctx_create(0, args.budget)
+    opts = mk.make_opts(chunk_size=chunk, window_bytes=args.window)
+    ref = [(i, t.clone()) for i, t in table] if args.check else None
+
+    dump_s, rest_s, kern_ns, kern_launches, rest_kern_ns = [], [], [], [], []
+    info = {}
+
+    def step(timed):
+        t0 = time.perf_counter()
+        rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+        t1 = time.perf_counter()
+        assert rc == 0, mk.ckpt_strerror(rc)
+        rc, rres = mk.ckpt_restore(ctx, img, table, opts=opts)
+        t2 = time.perf_counter()
+        assert rc == 0, (mk.ckpt_strerror(rc), rres.first_bad_chunk)
+        if timed:
+            dump_s.append(t1 - t0)
+            rest_s.append(t2 - t1)
+            kern_ns.append(res.ns_kernel)
+            kern_launches.append(res.windows)
+            rest_kern_ns.append(rres.ns_kernel)
+            info.update(D=res.n_payload, n_chunks=res.n_chunks, windows=res.windows, zero=res.n_zero,
+                        link_bytes=res.link_bytes)
+        img.free()
+        if ref is not None:
+            torch.cuda.synchronize()
+            for (_, a), (_, b) in zip(ref, table):
+                assert torch.equal(a, b)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(True)
+        print("step %d: dump %.3f s restore %.3f s" % (k, dump_s[-1], rest_s[-1]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mk.ckpt_ctx_destroy(ctx)
+
+    D, nc = info["D"], info["n_chunks"]
+    value = 2.0 * N * args.steps / elapsed / 1e9
+    dump_gbs = N / (sum(dump_s) / len(dump_s)) / 1e9
+    rest_gbs = N / (sum(rest_s) / len(rest_s)) / 1e9
+    alg = N + D + 9 * nc
+    k_avg = sum(kern_ns) / len(kern_ns) / 1e9                     # per dump, summed over its launches
+    achieved = alg / k_avg / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wdesc, "n_allocs": len(table), "N_bytes": N, "D_bytes": D, "chunk": chunk,
+                   "n_chunks": nc, "windows": info["windows"], "staging_budget": args.budget},
+        "dump_GBps": round(dump_gbs, 3),
+        "restore_GBps": round(rest_gbs, 3),
+        "dump_p50_ms": round(pct(dump_s, 50) * 1e3, 3),
+        "dump_p99_ms": round(pct(dump_s, 99) * 1e3, 3),
+        "restore_p50_ms": round(pct(rest_s, 50) * 1e3, 3),
+        "restore_p99_ms": round(pct(rest_s, 99) * 1e3, 3),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+        "dump_frac_of_link": round((info["link_bytes"] / (sum(dump_s) / len(dump_s)) / 1e9) / link["d2h"], 4),
+        "restore_frac_of_link": round((info["link_bytes"] / (sum(rest_s) / len(rest_s)) / 1e9) / link["h2d"], 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_chunks dump mode", "launches_per_dump": info["windows"],
+                     "avg_launch_ms": round(k_avg / max(1, info["windows"]) * 1e3, 4),
+                     "restore_kernel_GBps": round((D + D + N) / (sum(rest_kern_ns) / len(rest_kern_ns) / 1e9) / 1e9, 1)},
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(table, chunk, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

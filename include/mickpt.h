@@ -1,0 +1,164 @@
+/*
+ * mickpt.h -- C ABI of the MI355X checkpoint-image engine (libmickpt.so).
+ *
+ * The library turns a process's set of device allocations into a verified,
+ * restorable memory image in pinned host memory, and writes such an image
+ * back byte for byte. It follows the problem statement of transparent GPU
+ * checkpointing (CRIUgpu, arXiv 2502.16631):
+ *   - section 3.1.1: the checkpoint action copies the GPU state (device
+ *     memory) into host memory; the restore action puts device memory back;
+ *   - section 3.1.2: a buffer record carries handle, size, virtual address
+ *     and memory contents; a restore needs a compatible target;
+ *   - section 3.1: operations are dump, pre-dump (incremental) and restore,
+ *     and the exit callback reports success so that a failed operation can
+ *     be cleaned up (hence: no partial outputs);
+ *   - section 6: restores are deterministic (hence: 0-byte tolerance);
+ *   - section 7: incremental / differential checkpointing.
+ * The image format (v1), the CRC-32C chunk digests and the chunk grid are
+ * this library's definition; the paper specifies none of them.
+ *
+ * Plain C: only fixed-width integers and pointers. Device pointers are HIP
+ * device addresses; a stream is a hipStream_t passed as void* (NULL = the
+ * null stream). All functions are synchronous: they return when the result
+ * is complete on the host (dump) or the allocations are written and
+ * verified (restore).
+ */
+#ifndef MICKPT_H
+#define MICKPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define CKPT_OK         0
+#define CKPT_EINVAL    -1  /* bad argument: NULL, chunk size not a power of two in [16, 2^30],
+                              duplicate ids, misaligned device pointer, unknown flag          */
+#define CKPT_ENOMEM    -2  /* device staging, pinned host or descriptor allocation failed, or
+                              the request does not fit the staging budget                     */
+#define CKPT_EHIP      -3  /* a HIP call failed (ckpt_result.hip_error holds its code) or a
+                              kernel reported an internal error                               */
+#define CKPT_ECORRUPT  -4  /* image header / tables digest mismatch, inconsistent tables,
+                              or a restored chunk / allocation failed verification
+                              (ckpt_result.first_bad_chunk = lowest failing chunk)             */
+#define CKPT_EMISMATCH -5  /* allocation table differs from the image: count, id or size
+                              (the compatibility requirement of section 3.1.2)                */
+#define CKPT_EBASE     -6  /* delta without its base: restore target does not hold the base
+                              state (first_bad_chunk set), or merge with the wrong base       */
+#define CKPT_ETIMEOUT  -7  /* serving: request deadline passed before completion            */
+
+/* chunk kinds stored in an image */
+#define CKPT_KIND_ZERO      0
+#define CKPT_KIND_DATA      1
+#define CKPT_KIND_UNCHANGED 2
+
+/* ------------------------------------------------------------------ types */
+/* One device buffer (section 3.1.2 buffer record: handle, address, size).
+ * dev_ptr must be 16-byte aligned (hipMalloc and torch allocations are);
+ * size may be 0. id is the caller's stable handle and must be unique in a
+ * table. */
+typedef struct {
+    uint64_t id;
+    void*    dev_ptr;
+    uint64_t size;
+} ckpt_alloc;
+
+/* Caller-owned table; entries are kept in this order in the image. */
+typedef struct {
+    const ckpt_alloc* v;
+    uint32_t n;
+} ckpt_alloc_table;
+
+typedef struct ckpt_ctx ckpt_ctx;       /* device context: staging, streams, digest cache */
+typedef struct ckpt_image ckpt_image;   /* an image in pinned host memory                 */
+
+/* Tuning knobs. None of them changes the bytes of an image except
+ * chunk_size, which is recorded in its header. Pass NULL for defaults. */
+#define CKPT_OPT_PER_ALLOC  1u   /* launch the kernels once per allocation (baseline form)   */
+#define CKPT_OPT_GRAPH      2u   /* batched form: capture the device stage in a hipGraph and
+                                    replay it (cached per table shape)                      */
+#define CKPT_OPT_NO_TIMING  4u   /* skip per-stage device timing events                      */
+typedef struct {
+    uint32_t chunk_size;     /* bytes per chunk; 0 = 65536                                   */
+    uint32_t wg_threads;     /* work-group size of the chunk kernels; 0 = chosen per size   */
+    uint32_t copy_streams;   /* side streams for host-link copies; 0 = 2                     */
+    uint32_t slots;          /* staging ring slots; 0 = chosen from the budget              */
+    uint64_t window_bytes;   /* staging slot size; 0 = chosen from the budget               */
+    uint32_t flags;          /* CKPT_OPT_*                                                  */
+    uint32_t reserved;       /* must be 0                                                   */
+} ckpt_opts;
+
+/* Optional per-call report. */
+typedef struct {
+    uint64_t first_bad_chunk;   /* UINT64_MAX if none                                       */
+    int32_t  hip_error;         /* first failing hipError_t, 0 if none                      */
+    uint32_t windows;           /* staging windows used                                     */
+    uint64_t n_logical;         /* N: sum of allocation sizes                               */
+    uint64_t n_payload;         /* D: payload bytes                                         */
+    uint64_t n_chunks;
+    uint64_t n_zero, n_data, n_unchanged;
+    uint64_t link_bytes;        /* bytes moved over the host link                           */
+    uint64_t ns_total;          /* wall time of the call                                    */
+    uint64_t ns_kernel;         /* summed device time of the chunk kernels                  */
+    uint64_t ns_link;           /* wall time from first to last host-link copy              */
+    uint64_t reserved[4];
+} ckpt_result;
+
+/* ------------------------------------------------------------------ context */
+/* Create a context on HIP device `device`. staging_budget = bytes of device
+ * memory the context may use for staging windows (0 = 4 GiB). Returns
+ * CKPT_OK and *out, or an error and *out = NULL. */
+int  ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** out);
+/* Free a context and everything it owns except images. NULL is a no-op. */
+void ckpt_ctx_destroy(ckpt_ctx* ctx);
+
+/* ------------------------------------------------------------------ dump */
+/* Checkpoint (section 3.1.1 checkpoint action; section 3.1 pre-dump).
+ * Reads every allocation of `table` and writes a new image to *out.
+ * prev = NULL: full image. prev = an earlier image: delta image; a chunk
+ * whose CRC-32C equals the same chunk's digest in prev (allocation with the
+ * same id and size) is UNCHANGED and has no payload; all-zero chunks are
+ * ZERO either way. prev is borrowed and must have the same chunk size.
+ * The allocations must not be modified during the call (the caller's
+ * analogue of the paper's lock action). On failure *out = NULL and no
+ * allocation has been written. Work is ordered after prior work on stream. */
+int  ckpt_dump(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* prev,
+               ckpt_image** out, const ckpt_opts* opts, void* stream, ckpt_result* res);
+
+/* ------------------------------------------------------------------ restore */
+/* Restore (section 3.1.1 restore action; section 6 deterministic restore).
+ * Validates the image (header and tables digests, structure), checks that
+ * `table` matches it (count, ids, sizes in order: CKPT_EMISMATCH), then
+ * writes DATA chunks from the payload and zero-fills ZERO chunks,
+ * verifying every written chunk and every allocation against the image's
+ * digests. A delta image is applied in place: its UNCHANGED chunks must
+ * already hold the base state, which is checked before anything is written
+ * (CKPT_EBASE). After a CKPT_ECORRUPT the contents of the allocations are
+ * unspecified. */
+int  ckpt_restore(ckpt_ctx* ctx, const ckpt_image* img, const ckpt_alloc_table* table,
+                  const ckpt_opts* opts, void* stream, ckpt_result* res);
+
+/* ------------------------------------------------------------------ host ops */
+/* Fold a delta into the full image of its base (host memory only): the
+ * result equals a full dump of the delta's state. CKPT_EINVAL if base is a
+ * delta or delta is not one, CKPT_EBASE if delta was not taken against
+ * base. */
+int  ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_image** out);
+/* Borrow the bytes of an image (valid until ckpt_image_free). */
+int  ckpt_image_bytes(const ckpt_image* img, const void** p, uint64_t* n);
+/* Copy n bytes into a new image after validating header, tables digest and
+ * structure (CKPT_ECORRUPT if invalid). */
+int  ckpt_image_import(const void* p, uint64_t n, ckpt_image** out);
+/* Free an image. NULL is a no-op. */
+void ckpt_image_free(ckpt_image* img);
+/* Static description of an error code. */
+const char* ckpt_strerror(int code);
+/* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes. */
+uint32_t ckpt_crc32c(const void* p, uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MICKPT_H */

@@ -1,0 +1,20 @@
+#!/bin/bash
+# Build libmickpt.so for gfx950 in-tree (host compilers only; no GPU needed).
+set -euo pipefail
+HERE="$(cd "$(dirname "$0")" && pwd)"
+SRC="$HERE/csrc"
+OUT="$HERE/libmickpt.so"
+BUILD="$HERE/_build"
+mkdir -p "$BUILD"
+FLAGS=(--offload-arch=gfx950 -O3 -std=c++17 -fPIC -Wall -Wno-unused-result -Wno-unused-value -Wno-pass-failed
+       -Xclang -target-feature -Xclang -packed-fp32-ops)
+hipcc "${FLAGS[@]}" -c "$SRC/kernels.hip" -o "$BUILD/kernels.o" &
+p1=$!
+hipcc "${FLAGS[@]}" -c "$SRC/runtime.hip" -o "$BUILD/runtime.o" &
+p2=$!
+hipcc -O2 -std=c++17 -fPIC -Wall -c "$SRC/hostmath.cpp" -o "$BUILD/hostmath.o" &
+p3=$!
+wait $p1; wait $p2; wait $p3
+hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/hostmath.o" -lpthread
+mv "$OUT.tmp" "$OUT"
+echo "built $OUT"

@@ -1,0 +1,76 @@
+// Launch interface of the chunk kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace mk {
+
+enum Mode : int { kModeDump = 0, kModeDigest = 1, kModeVerify = 2, kModeRestore = 3 };
+
+// One launch of the chunk engine over global chunks [g0, g1).
+struct ChunkJob {
+    const AllocDesc* allocs;
+    uint32_t n_allocs;
+    uint32_t C;                  // chunk size
+    uint64_t g0, g1;
+    const EngineConsts* ec;      // tables for (T, C)
+    uint32_t* crc_out;           // dump / digest: digest of chunk g at [g]
+    uint8_t* kind_out;           // dump: kind of chunk g at [g]
+    const uint8_t* kind_in;      // verify / restore: kind of chunk g
+    const uint32_t* ref_crc;     // verify / restore: expected digest of chunk g
+    const uint32_t* prev_crc;    // dump: previous digest table or nullptr
+    uint8_t* slot;               // staging window (dump: written, restore: read)
+    const uint64_t* off;         // restore: payload offset of chunk g
+    uint64_t slot_base;          // restore: payload offset of the window start
+    uint64_t* status;            // dump: look-back status, indexed by g - g0
+    uint32_t* ticket;            // zero before launch
+    uint64_t* wtotal;            // dump: payload bytes of the window
+    unsigned long long* bad;     // verify / restore: lowest failing chunk (init ~0)
+    uint32_t* err;               // internal error flag (look-back time-out)
+    uint32_t epoch;              // look-back epoch of this launch (1 .. 2^22-1)
+    uint32_t pad;
+};
+
+// Payload offsets of every chunk from the kind table (restore).
+struct OffJob {
+    const AllocDesc* allocs;
+    uint32_t n_allocs;
+    uint32_t C;
+    uint64_t n_chunks;
+    const uint8_t* kind;
+    uint64_t* off;               // [n_chunks]
+    uint64_t per_window;         // chunks per staging window G
+    uint64_t* wb;                // [W + 1] payload offset at each window start, wb[W] = total
+    uint64_t n_windows;          // W
+    uint64_t* status;            // look-back, one word per tile
+    uint32_t* ticket;
+    unsigned long long* counts;  // [4]: zero, data, unchanged, invalid (zeroed before launch)
+    uint32_t* err;
+    uint32_t epoch;
+    uint32_t pad;
+};
+
+// Per-allocation combine of chunk digests into the whole-allocation CRC.
+enum CombineMode : int { kCombineWrite = 0, kCombineCheck = 1, kCombineOut = 2 };
+struct CombineJob {
+    const AllocDesc* allocs;
+    uint32_t n_allocs;
+    uint32_t C;
+    const uint32_t* crc;         // chunk digests (global index)
+    const EngineConsts* ec;      // full_x and x2n for this C
+    uint8_t* recs;               // write: AllocRec[n] (32 bytes each); check: read alloc_crc
+    uint32_t* out;               // out mode: CRC of allocation a at [a]
+    unsigned long long* bad;     // check mode
+    int mode;
+    int pad;
+};
+
+bool tile_supported(int T, int K);
+hipError_t launch_chunks(int T, int K, int mode, const ChunkJob& job, int grid, hipStream_t s);
+hipError_t chunks_occupancy(int T, int K, int mode, int* blocks_per_cu);
+hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s);
+hipError_t launch_combine(const CombineJob& job, hipStream_t s);
+hipError_t launch_fill64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
+}  // namespace mk

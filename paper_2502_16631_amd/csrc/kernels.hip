@@ -1,0 +1,620 @@
+// Chunk kernels for gfx950 (CDNA4, wave64).
+//
+// One persistent kernel family processes the chunk grid of an allocation
+// table: each work-group takes chunk tickets in increasing order from an
+// atomic counter, so every chunk below its ticket has already been taken by
+// a running work-group (this is what makes the decoupled look-back safe).
+//
+// Per chunk, the T threads of a work-group read the chunk as K rows of
+// 16 T bytes: thread t owns the 16-byte block at offset r*16T + 16t of each
+// row r, so every row is one fully coalesced 128-bit load per thread. The
+// CRC-32C of the chunk is computed without moving the data between lanes:
+// lane t keeps the raw CRC of its own interleaved stream (its blocks, with
+// the other lanes' bytes read as zeros). Per row the running value is
+// advanced over the 16T bytes of the row with four lookups (jt) and the
+// block's 16 bytes are folded in with sixteen lookups (dt); both tables
+// live in LDS. At the end lane t's value is shifted to the end of the chunk
+// (multiplied by x^(8*16(T-1-t))) and the lanes' values are xor-reduced.
+// Modes:
+//   dump    - digest + zero test + unchanged test against the previous
+//             digest table, then the chunk's payload offset from a decoupled
+//             look-back over the chunks before it, then the chunk is stored
+//             from registers into the staging window (single pass: the data
+//             is read from HBM once);
+//   digest  - digest only (used for the image's table digests);
+//   verify  - digest of UNCHANGED chunks compared with the image (delta
+//             restore checks that the target holds the base);
+//   restore - DATA chunks read from the staging window, stored to their
+//             allocation and verified on the data in registers; ZERO chunks
+//             zero-filled.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace mk {
+namespace {
+
+constexpr uint32_t kMaxSpins = 1u << 24;
+
+typedef __attribute__((address_space(1))) uint64_t gu64;
+__device__ inline void st_relaxed(uint64_t* p, uint64_t v) {
+    __hip_atomic_store((gu64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t ld_relaxed(uint64_t* p) {
+    return __hip_atomic_load((gu64*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+__device__ inline uint32_t wave_xor(uint32_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v ^= __shfl_xor(v, m);
+    return v;
+}
+
+// Decoupled look-back (single-pass prefix scan): the calling wave publishes
+// its aggregate `agg` at position idx, sums the aggregates of its
+// predecessors back to the nearest published inclusive prefix, publishes its
+// own inclusive prefix and returns the exclusive one. All 64 lanes call it.
+__device__ uint64_t lookback(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t tag = (uint64_t)(epoch & kEpochMask) << 40;
+    if (idx == 0) {
+        if (lane == 0) st_relaxed(&status[0], kStInc | tag | agg);
+        return 0;
+    }
+    if (lane == 0) st_relaxed(&status[idx], kStAgg | tag | agg);
+    uint64_t excl = 0;
+    int64_t base = (int64_t)idx - 1;
+    for (;;) {
+        const int64_t j = base - lane;
+        uint64_t w = kStInc | tag;          // before the start: inclusive 0
+        if (j >= 0) {
+            uint32_t spins = 0;
+            for (;;) {
+                w = ld_relaxed(&status[j]);
+                if ((w >> 62) != 0 && ((w >> 40) & kEpochMask) == (epoch & kEpochMask)) break;
+                if (++spins > kMaxSpins) {   // bounded wait: report, never hang
+                    atomicOr(err, 1u);
+                    w = kStInc | tag;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        const bool inc = (w >> 62) == 2;
+        const uint64_t val = w & kStValueMask;
+        const uint64_t incmask = __ballot(inc);
+        if (incmask) {
+            const int first = __ffsll((unsigned long long)incmask) - 1;
+            excl += wave_sum_u64(lane <= first ? val : 0);
+            break;
+        }
+        excl += wave_sum_u64(val);
+        base -= 64;
+    }
+    if (lane == 0) st_relaxed(&status[idx], kStInc | tag | (excl + agg));
+    return excl;
+}
+
+// last allocation whose first chunk is <= g (empty allocations share their
+// successor's first chunk and are therefore never selected)
+__device__ inline uint32_t find_alloc(const AllocDesc* a, uint32_t n, uint64_t g) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid].first <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// 128-bit data type. Accesses go through address-space-1 (global) pointers:
+// the chunk pointers come from descriptors (integers), and without an
+// explicit address space the compiler emits flat accesses.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4u gcv4;
+typedef __attribute__((address_space(1))) v4u gv4;
+typedef __attribute__((address_space(1))) const uint8_t gcu8;
+typedef __attribute__((address_space(1))) uint8_t gu8;
+__device__ inline v4u gload(const uint8_t* p) { return *(gcv4*)(p); }
+__device__ inline void gstore(uint8_t* p, v4u v) { *(gv4*)(p) = v; }
+__device__ inline v4u vzero() { return (v4u){0u, 0u, 0u, 0u}; }
+
+__device__ inline v4u load_partial(const uint8_t* p, uint32_t n) {   // 0 < n < 16
+    uint64_t lo = 0, hi = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t b = ((gcu8*)p)[i];
+        if (i < 8) lo |= b << (8 * i); else hi |= b << (8 * (i - 8));
+    }
+    return (v4u){(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+}
+
+__device__ inline void store_partial(uint8_t* p, v4u v, uint32_t n) {   // 0 < n < 16
+    const uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    const uint64_t hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    for (uint32_t i = 0; i < n; ++i) ((gu8*)p)[i] = (uint8_t)((i < 8 ? lo >> (8 * i) : hi >> (8 * (i - 8))) & 0xFF);
+}
+
+// keep the low n bytes of v (0 < n < 16); *dropped |= the other bytes
+__device__ inline v4u keep_low(v4u v, uint32_t n, uint32_t* dropped) {
+    v4u out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int nb = (int)n - 4 * i;   // bytes of word i to keep
+        const uint32_t m = nb >= 4 ? 0xFFFFFFFFu : nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u);
+        out[i] = v[i] & m;
+        *dropped |= v[i] & ~m;
+    }
+    return out;
+}
+
+__device__ inline uint32_t or4(v4u v) { return v.x | v.y | v.z | v.w; }
+
+__device__ inline uint32_t blk16(v4u v, const uint32_t* dt) {
+    return dt[0 * 256 + (v.x & 255)] ^ dt[1 * 256 + ((v.x >> 8) & 255)] ^
+           dt[2 * 256 + ((v.x >> 16) & 255)] ^ dt[3 * 256 + (v.x >> 24)] ^
+           dt[4 * 256 + (v.y & 255)] ^ dt[5 * 256 + ((v.y >> 8) & 255)] ^
+           dt[6 * 256 + ((v.y >> 16) & 255)] ^ dt[7 * 256 + (v.y >> 24)] ^
+           dt[8 * 256 + (v.z & 255)] ^ dt[9 * 256 + ((v.z >> 8) & 255)] ^
+           dt[10 * 256 + ((v.z >> 16) & 255)] ^ dt[11 * 256 + (v.z >> 24)] ^
+           dt[12 * 256 + (v.w & 255)] ^ dt[13 * 256 + ((v.w >> 8) & 255)] ^
+           dt[14 * 256 + ((v.w >> 16) & 255)] ^ dt[15 * 256 + (v.w >> 24)];
+}
+
+__device__ inline uint32_t jump(uint32_t acc, const uint32_t* jt) {
+    return jt[acc & 255] ^ jt[256 + ((acc >> 8) & 255)] ^ jt[512 + ((acc >> 16) & 255)] ^ jt[768 + (acc >> 24)];
+}
+
+template <int K>
+__device__ inline uint32_t crc_rows(const v4u (&v)[K], uint32_t acc, bool cont, const uint32_t* dt,
+                                    const uint32_t* jt) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        if (r > 0 || cont) acc = jump(acc, jt);
+        acc ^= blk16(v[r], dt);
+        // one row of lookups in flight at a time: keeps the register
+        // footprint near the data itself (other waves hide the latency)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// Load one pass (K rows) of a chunk, zero-extending beyond `len` valid bytes.
+template <int T, int K>
+__device__ inline void load_rows(v4u (&v)[K], const uint8_t* base, uint64_t len, uint32_t tid, bool active) {
+    constexpr uint32_t R = 16u * T;
+    if (!active) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) v[r] = vzero();
+        return;
+    }
+    if (len >= (uint64_t)R * K) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) v[r] = gload(base + r * R + 16u * tid);
+    } else {
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const uint32_t o = r * R + 16u * tid;
+            if (o + 16 <= len) v[r] = gload(base + o);
+            else if (o < len) v[r] = load_partial(base + o, (uint32_t)(len - o));
+            else v[r] = vzero();
+        }
+    }
+}
+
+// Load one pass of a payload record from staging: whole 16-byte blocks up to
+// round16(len) exist; bytes beyond len are padding that must be zero.
+template <int T, int K>
+__device__ inline void load_rows_staged(v4u (&v)[K], const uint8_t* base, uint64_t len, uint32_t tid, bool active,
+                                        uint32_t* padbad) {
+    constexpr uint32_t R = 16u * T;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const uint32_t o = r * R + 16u * tid;
+        if (!active || o >= len) {
+            v[r] = vzero();
+        } else {
+            v[r] = gload(base + o);
+            if (o + 16 > len) v[r] = keep_low(v[r], (uint32_t)(len - o), padbad);
+        }
+    }
+}
+
+// Store the valid bytes of one pass (len valid bytes from base).
+template <int T, int K>
+__device__ inline void store_rows_exact(const v4u (&v)[K], uint8_t* base, uint64_t len, uint32_t tid, bool active) {
+    constexpr uint32_t R = 16u * T;
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const uint32_t o = r * R + 16u * tid;
+        if (o + 16 <= len) gstore(base + o, v[r]);
+        else if (o < len) store_partial(base + o, v[r], (uint32_t)(len - o));
+    }
+}
+
+// Store whole 16-byte blocks of one pass up to len16 bytes (payload records).
+template <int T, int K>
+__device__ inline void store_rows_padded(const v4u (&v)[K], uint8_t* base, uint64_t len16, uint32_t tid, bool active) {
+    constexpr uint32_t R = 16u * T;
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const uint32_t o = r * R + 16u * tid;
+        if (o < len16) gstore(base + o, v[r]);
+    }
+}
+
+template <int NW>
+__device__ inline uint32_t wg_xor(uint32_t x, uint32_t* s_red) {
+    x = wave_xor(x);
+    if constexpr (NW > 1) {
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = x;
+        __syncthreads();
+        x = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) x ^= s_red[w];
+    }
+    return x;
+}
+
+// Register cap: 128 VGPRs (4 waves per SIMD) for every shape; the 8-row
+// shapes hold 32 VGPRs of chunk data between load and store.
+template <int T, int K, int MODE>
+__global__ void __launch_bounds__(T < 64 ? 64 : T) __attribute__((amdgpu_waves_per_eu(4)))
+k_chunks(ChunkJob job) {
+    constexpr int NT = T < 64 ? 64 : T;
+    constexpr int NW = NT / 64;
+    constexpr uint32_t TILE = 16u * T * K;
+    __shared__ uint32_t s_dt[16 * 256];
+    __shared__ uint32_t s_jt[4 * 256];
+    __shared__ uint32_t s_red[NW];
+    __shared__ uint32_t s_tk[2];
+    __shared__ uint64_t s_off;
+
+    const int tid = threadIdx.x;
+    const bool active = T >= 64 || tid < T;
+    for (int i = tid; i < 16 * 256; i += NT) s_dt[i] = job.ec->dt[i];
+    for (int i = tid; i < 4 * 256; i += NT) s_jt[i] = job.ec->jt[i];
+    const uint32_t lanec = active ? job.ec->lane[tid] : 0u;
+    const uint32_t full_init = job.ec->full_init;
+    const uint32_t C = job.C;
+    const uint32_t log2c = 31 - __builtin_clz(C);
+    const uint32_t P = C / TILE;        // passes per chunk (C is a multiple of TILE)
+    __syncthreads();
+
+    for (uint32_t it = 0;; ++it) {
+        if (tid == 0) s_tk[it & 1] = atomicAdd(job.ticket, 1u);
+        __syncthreads();
+        const uint64_t g = job.g0 + (uint64_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
+        if (g >= job.g1) break;
+        // Opaque per-chunk copies of per-lane values: without them the
+        // compiler hoists 32 multiples of the lane constant and one address
+        // per row out of the loop, which costs ~50 VGPRs per lane.
+        uint32_t lc = lanec;
+        uint32_t ltid = (uint32_t)tid;
+        asm volatile("" : "+v"(lc), "+v"(ltid));
+
+        uint8_t kd_in = kData;
+        if constexpr (MODE == kModeVerify || MODE == kModeRestore) {
+            kd_in = job.kind_in[g];
+            if (MODE == kModeVerify && kd_in != kUnchanged) continue;
+            if (MODE == kModeRestore && kd_in == kUnchanged) continue;
+        }
+        const uint32_t a = find_alloc(job.allocs, job.n_allocs, g);
+        const AllocDesc ad = job.allocs[a];
+        const uint64_t k = g - ad.first;
+        const uint64_t nk = (ad.size + C - 1) >> log2c;
+        const uint32_t len = (k + 1 == nk) ? ad.tail_len : C;
+        const bool full = len == C;
+        const uint32_t init = full ? full_init : ad.tail_init;
+        uint8_t* const aptr = reinterpret_cast<uint8_t*>(ad.ptr) + (k << log2c);
+
+        if constexpr (MODE == kModeRestore) {
+            if (kd_in == kZero) {
+                const v4u z = vzero();
+                v4u zv[K];
+#pragma unroll
+                for (int r = 0; r < K; ++r) zv[r] = z;
+                for (uint32_t p = 0; p < P; ++p) {
+                    const uint64_t lp = (uint64_t)p * TILE;
+                    if (lp >= len) break;
+                    store_rows_exact<T, K>(zv, aptr + lp, len - lp, ltid, active);
+                }
+                if (tid == 0 && job.ref_crc[g] != ~init) atomicMin(job.bad, (unsigned long long)g);
+                continue;
+            }
+            const uint8_t* src = job.slot + (job.off[g] - job.slot_base);
+            uint32_t acc = 0, padbad = 0;
+            for (uint32_t p = 0; p < P; ++p) {
+                const uint64_t lp = (uint64_t)p * TILE;
+                v4u v[K];
+                const uint64_t rem = len > lp ? len - lp : 0;
+                load_rows_staged<T, K>(v, src + lp, rem, ltid, active, &padbad);
+                if (rem) store_rows_exact<T, K>(v, aptr + lp, rem, ltid, active);
+                acc = crc_rows<K>(v, acc, p > 0, s_dt, s_jt);
+            }
+            uint32_t raw = wg_xor<NW>(gf_mul(acc, lc), s_red);
+            const int pb = __syncthreads_or(padbad != 0);
+            if (!full) raw = gf_mul(raw, ad.tail_unshift);
+            const uint32_t crc = ~(raw ^ init);
+            if (tid == 0 && (crc != job.ref_crc[g] || pb)) atomicMin(job.bad, (unsigned long long)g);
+            continue;
+        } else {
+            v4u v[K];
+            uint32_t acc = 0, orw = 0;
+            int any;
+            if (P == 1) {
+                load_rows<T, K>(v, aptr, len, ltid, active);
+                if constexpr (MODE == kModeDump) {
+#pragma unroll
+                    for (int r = 0; r < K; ++r) orw |= or4(v[r]);
+                    any = __syncthreads_or(orw != 0);
+                    if (any) acc = crc_rows<K>(v, 0, false, s_dt, s_jt);
+                } else {
+                    any = 1;
+                    acc = crc_rows<K>(v, 0, false, s_dt, s_jt);
+                }
+            } else {
+                for (uint32_t p = 0; p < P; ++p) {
+                    const uint64_t lp = (uint64_t)p * TILE;
+                    load_rows<T, K>(v, aptr + lp, len > lp ? len - lp : 0, ltid, active);
+#pragma unroll
+                    for (int r = 0; r < K; ++r) orw |= or4(v[r]);
+                    acc = crc_rows<K>(v, acc, p > 0, s_dt, s_jt);
+                }
+                any = (MODE == kModeDump) ? __syncthreads_or(orw != 0) : 1;
+            }
+            uint32_t crc = ~init;
+            if (any) {
+                uint32_t raw = wg_xor<NW>(gf_mul(acc, lc), s_red);
+                if (!full) raw = gf_mul(raw, ad.tail_unshift);
+                crc = ~(raw ^ init);
+            }
+            if constexpr (MODE == kModeDigest) {
+                if (tid == 0) job.crc_out[g] = crc;
+                continue;
+            }
+            if constexpr (MODE == kModeVerify) {
+                if (tid == 0 && crc != job.ref_crc[g]) atomicMin(job.bad, (unsigned long long)g);
+                continue;
+            }
+            if constexpr (MODE == kModeDump) {
+                uint8_t kd = kData;
+                if (!any) kd = kZero;
+                else if (job.prev_crc != nullptr && ad.prev_first != ~0ull && job.prev_crc[ad.prev_first + k] == crc)
+                    kd = kUnchanged;
+                if (tid == 0) {
+                    job.crc_out[g] = crc;
+                    job.kind_out[g] = kd;
+                }
+                const uint64_t len16 = (len + 15u) & ~15u;
+                const uint64_t plen = kd == kData ? len16 : 0;
+                if (tid < 64) {
+                    const uint64_t e = lookback(job.status, g - job.g0, plen, job.epoch, job.err);
+                    if (tid == 0) s_off = e;
+                }
+                __syncthreads();
+                const uint64_t excl = s_off;
+                if (kd == kData) {
+                    uint8_t* dst = job.slot + excl;
+                    if (P == 1) {
+                        store_rows_padded<T, K>(v, dst, len16, ltid, active);
+                    } else {
+                        for (uint32_t p = 0; p < P; ++p) {
+                            const uint64_t lp = (uint64_t)p * TILE;
+                            if (lp >= len16) break;
+                            load_rows<T, K>(v, aptr + lp, len - lp, ltid, active);
+                            store_rows_padded<T, K>(v, dst + lp, len16 - lp, ltid, active);
+                        }
+                    }
+                }
+                if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_offsets(OffJob job) {
+    __shared__ uint32_t s_tk[2];
+    __shared__ uint64_t s_wsum[4];
+    __shared__ uint64_t s_off;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (uint32_t it = 0;; ++it) {
+        if (tid == 0) s_tk[it & 1] = atomicAdd(job.ticket, 1u);
+        __syncthreads();
+        const uint64_t tile = __builtin_amdgcn_readfirstlane(s_tk[it & 1]);
+        const uint64_t g0 = tile * 256;
+        if (g0 >= job.n_chunks) break;
+        const uint64_t g = g0 + tid;
+        uint64_t plen = 0;
+        uint32_t cz = 0, cd = 0, cu = 0, ci = 0;
+        if (g < job.n_chunks) {
+            const uint8_t kd = job.kind[g];
+            const uint32_t a = find_alloc(job.allocs, job.n_allocs, g);
+            const uint64_t first = job.allocs[a].first, size = job.allocs[a].size;
+            const uint64_t nk = (size + job.C - 1) / job.C;
+            const uint64_t len = (g - first + 1 == nk) ? job.allocs[a].tail_len : job.C;
+            if (kd == kData) { plen = (len + 15) & ~15ull; cd = 1; }
+            else if (kd == kZero) cz = 1;
+            else if (kd == kUnchanged) cu = 1;
+            else ci = 1;
+        }
+        // block scan of plen
+        uint64_t x = plen;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        // kind counts
+        const uint64_t bz = __ballot(cz), bd = __ballot(cd), bu = __ballot(cu), bi = __ballot(ci);
+        if (lane == 0) {
+            if (bz) atomicAdd(&job.counts[0], (unsigned long long)__popcll(bz));
+            if (bd) atomicAdd(&job.counts[1], (unsigned long long)__popcll(bd));
+            if (bu) atomicAdd(&job.counts[2], (unsigned long long)__popcll(bu));
+            if (bi) atomicAdd(&job.counts[3], (unsigned long long)__popcll(bi));
+        }
+        __syncthreads();
+        uint64_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? s_wsum[w] : 0;
+            total += s_wsum[w];
+        }
+        const uint64_t local = before + x - plen;
+        if (tid < 64) {
+            const uint64_t e = lookback(job.status, tile, total, job.epoch, job.err);
+            if (tid == 0) s_off = e;
+        }
+        __syncthreads();
+        const uint64_t o = s_off + local;
+        if (g < job.n_chunks) {
+            job.off[g] = o;
+            if (g % job.per_window == 0) job.wb[g / job.per_window] = o;
+            if (g + 1 == job.n_chunks) job.wb[job.n_windows] = o + plen;
+        }
+    }
+}
+
+__device__ inline uint32_t xpow8(uint64_t n, const uint32_t* x2n) {   // x^(8n)
+    uint32_t r = kOne;
+    for (int b = 3; n; n >>= 1, ++b)
+        if (n & 1) r = gf_mul(r, x2n[b]);
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_combine(CombineJob job) {
+    __shared__ uint32_t s_red[4];
+    __shared__ uint32_t s_x2n[64];
+    const int tid = threadIdx.x;
+    if (tid < 64) s_x2n[tid] = job.ec->x2n[tid];
+    __syncthreads();
+    const uint32_t a = blockIdx.x;
+    const AllocDesc ad = job.allocs[a];
+    const uint64_t C = job.C;
+    const uint64_t nk = (ad.size + C - 1) / C;
+    const uint64_t m = (nk + 255) / 256;
+    const uint64_t k0 = (uint64_t)tid * m, k1 = k0 + m < nk ? k0 + m : nk;
+    uint32_t contrib = 0;
+    if (k0 < k1) {
+        const uint32_t full_x = job.ec->full_x;
+        uint32_t acc = 0;
+        for (uint64_t k = k0; k < k1; ++k) {
+            const uint32_t xk = (k + 1 == nk) ? ad.tail_x : full_x;
+            acc = gf_mul(acc, xk) ^ job.crc[ad.first + k];
+        }
+        const uint64_t end = k1 == nk ? ad.size : k1 * C;
+        contrib = gf_mul(acc, xpow8(ad.size - end, s_x2n));
+    }
+    const uint32_t crc = wg_xor<4>(contrib, s_red);
+    if (tid == 0) {
+        if (job.mode == kCombineWrite) {
+            uint8_t* rec = job.recs + 32ull * a;
+            reinterpret_cast<uint64_t*>(rec)[0] = ad.id;
+            reinterpret_cast<uint64_t*>(rec)[1] = ad.size;
+            reinterpret_cast<uint64_t*>(rec)[2] = ad.first;
+            reinterpret_cast<uint32_t*>(rec)[6] = crc;
+            reinterpret_cast<uint32_t*>(rec)[7] = 0;
+        } else if (job.mode == kCombineCheck) {
+            const uint32_t want = reinterpret_cast<const uint32_t*>(job.recs + 32ull * a)[6];
+            if (want != crc) atomicMin(job.bad, (unsigned long long)ad.first);
+        } else {
+            job.out[a] = crc;
+        }
+    }
+}
+
+__global__ void k_fill64(uint64_t* p, uint64_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill32(uint32_t* p, uint32_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <int T, int K>
+hipError_t launch_tk(int mode, const ChunkJob& job, int grid, hipStream_t s) {
+    constexpr int NT = T < 64 ? 64 : T;
+    switch (mode) {
+        case kModeDump: hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, job); break;
+        case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, job); break;
+        case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, job); break;
+        case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, job); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int T, int K>
+hipError_t occ_tk(int mode, int* n) {
+    constexpr int NT = T < 64 ? 64 : T;
+    switch (mode) {
+        case kModeDump: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDump>, NT, 0);
+        case kModeDigest: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDigest>, NT, 0);
+        case kModeVerify: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeVerify>, NT, 0);
+        case kModeRestore: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeRestore>, NT, 0);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// the work-group shapes that are compiled
+#define MK_TILES(X) \
+    X(1, 1) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(32, 1) \
+    X(64, 1) X(64, 4) X(256, 1) X(256, 4) X(256, 8) X(512, 4) X(512, 8) X(1024, 4) X(1024, 8)
+
+}  // namespace
+
+bool tile_supported(int T, int K) {
+#define MK_TEST(t, k) if (T == t && K == k) return true;
+    MK_TILES(MK_TEST)
+#undef MK_TEST
+    return false;
+}
+
+hipError_t launch_chunks(int T, int K, int mode, const ChunkJob& job, int grid, hipStream_t s) {
+#define MK_LAUNCH(t, k) if (T == t && K == k) return launch_tk<t, k>(mode, job, grid, s);
+    MK_TILES(MK_LAUNCH)
+#undef MK_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t chunks_occupancy(int T, int K, int mode, int* n) {
+#define MK_OCC(t, k) if (T == t && K == k) return occ_tk<t, k>(mode, n);
+    MK_TILES(MK_OCC)
+#undef MK_OCC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_offsets, dim3(grid), dim3(256), 0, s, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineJob& job, hipStream_t s) {
+    if (job.n_allocs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine, dim3(job.n_allocs), dim3(256), 0, s, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill64, dim3(blocks < 1024 ? (unsigned)blocks : 1024u), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill32, dim3(blocks < 1024 ? (unsigned)blocks : 1024u), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace mk

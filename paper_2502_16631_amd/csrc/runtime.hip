@@ -1,0 +1,1219 @@
+// Host runtime of libmickpt: contexts, the dump and restore pipelines over a
+// ring of device staging windows, image objects, merge and import.
+//
+// Dump of one table (paper section 3.1.1, checkpoint action):
+//   1. descriptors: per allocation the first chunk, the tail constants and
+//      the matching allocation of the previous image;
+//   2. per staging window (a range of whole chunks): one launch of the chunk
+//      engine in dump mode -- CRC, zero / unchanged test, look-back offsets
+//      and the gather into the window, in a single read of the data;
+//   3. the window's payload length is read back and the window is copied to
+//      the pinned image on a side stream while the next window is processed;
+//   4. per-allocation CRCs (combine), table digests, tables copied out,
+//      header written on the host.
+// Restore (section 3.1.1, restore action; section 6, deterministic restore):
+//   1. header checked on the host; tables uploaded and their digest checked;
+//      payload offsets of every chunk from a scan of the kinds;
+//   2. a delta first verifies that every UNCHANGED chunk of the target holds
+//      the recorded digest (before anything is written);
+//   3. per window: the payload slice is copied to a staging window on a side
+//      stream, then scattered to the allocations and verified;
+//   4. per-allocation CRCs are checked.
+#include <hip/hip_runtime.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/mickpt.h"
+#include "hostmath.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace mk;
+
+namespace {
+
+constexpr uint64_t kNoChunk = ~0ull;
+constexpr uint64_t kHeader = 64;
+constexpr uint32_t kDefaultChunk = 65536;
+constexpr uint64_t kDefaultBudget = 4ull << 30;
+
+uint64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+uint64_t round16(uint64_t n) { return (n + 15) & ~15ull; }
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+bool valid_chunk(uint64_t c) { return c >= 16 && c <= (1ull << 30) && (c & (c - 1)) == 0; }
+uint64_t tables_len(uint64_t n, uint64_t nc) { return round16(32 * n + 5 * nc); }
+
+void put32(uint8_t* p, uint32_t v) { memcpy(p, &v, 4); }
+void put64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
+uint32_t get32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
+uint64_t get64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
+
+std::atomic<uint64_t> g_uid{1};
+
+// ------------------------------------------------------------ pinned pool
+// Freed image buffers are kept for reuse: pinning tens of GB costs seconds.
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<uint64_t, void*> free_;   // capacity -> buffer
+    uint64_t cached = 0;
+    static constexpr uint64_t kMaxCached = 96ull << 30;
+    void* get(uint64_t cap, uint64_t* got) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_.lower_bound(cap);
+            if (it != free_.end() && it->first <= cap + cap / 4 + (64ull << 20)) {
+                void* p = it->second;
+                *got = it->first;
+                cached -= it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) return nullptr;
+        *got = cap;
+        return p;
+    }
+    void put(void* p, uint64_t cap) {
+        std::lock_guard<std::mutex> g(mu);
+        while (cached + cap > kMaxCached && !free_.empty()) {
+            auto it = free_.begin();
+            hipHostFree(it->second);
+            cached -= it->first;
+            free_.erase(it);
+        }
+        if (cached + cap > kMaxCached) { hipHostFree(p); return; }
+        free_.emplace(cap, p);
+        cached += cap;
+    }
+};
+PinnedPool& pool() {
+    static PinnedPool* p = new PinnedPool();   // never destroyed: buffers may outlive statics
+    return *p;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ image
+struct ckpt_image {
+    uint8_t* p = nullptr;
+    uint64_t n = 0;
+    uint64_t cap = 0;
+    uint64_t uid = 0;
+};
+
+static ckpt_image* image_new(uint64_t cap) {
+    ckpt_image* im = new ckpt_image();
+    uint64_t got = 0;
+    im->p = static_cast<uint8_t*>(pool().get(cap, &got));
+    if (!im->p) { delete im; return nullptr; }
+    im->cap = got;
+    im->uid = g_uid.fetch_add(1);
+    return im;
+}
+
+// ------------------------------------------------------------ parsed image
+namespace mk {
+
+int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_tables) {
+    if (len < kHeader || memcmp(img, "MICKPT01", 8) != 0) return CKPT_ECORRUPT;
+    if (host_crc32c(img, 60) != get32(img + 60)) return CKPT_ECORRUPT;
+    const uint32_t version = get32(img + 8);
+    v->flags = get32(img + 12);
+    v->C = get32(img + 16);
+    v->n_allocs = get32(img + 20);
+    v->n_chunks = get64(img + 24);
+    v->D = get64(img + 32);
+    v->base_state = get32(img + 40);
+    const uint32_t reserved = get32(img + 44);
+    v->N = get64(img + 48);
+    v->tables_crc = get32(img + 56);
+    if (version != 1 || (v->flags & ~1u) || reserved != 0 || !valid_chunk(v->C)) return CKPT_ECORRUPT;
+    if (v->n_chunks > (1ull << 40) || v->n_allocs > (1u << 24)) return CKPT_ECORRUPT;
+    v->tl = tables_len(v->n_allocs, v->n_chunks);
+    if (len != kHeader + v->tl + v->D) return CKPT_ECORRUPT;
+    v->recs = img + kHeader;
+    v->crcs = v->recs + 32ull * v->n_allocs;
+    v->kinds = v->crcs + 4 * v->n_chunks;
+    v->payload = img + kHeader + v->tl;
+    // allocation records: chunk grid, sizes, padding
+    uint64_t g = 0, total = 0;
+    for (uint64_t a = 0; a < v->n_allocs; ++a) {
+        const uint8_t* r = v->recs + 32 * a;
+        if (get64(r + 16) != g || get32(r + 28) != 0) return CKPT_ECORRUPT;
+        g += ceil_div(get64(r + 8), v->C);
+        total += get64(r + 8);
+        if (g > v->n_chunks) return CKPT_ECORRUPT;
+    }
+    if (g != v->n_chunks || total != v->N) return CKPT_ECORRUPT;
+    if (!(v->flags & 1u) && v->base_state != 0) return CKPT_ECORRUPT;
+    for (const uint8_t* p = v->kinds + v->n_chunks; p < v->recs + v->tl; ++p)
+        if (*p) return CKPT_ECORRUPT;
+    if (check_tables) {
+        if (host_crc32c(v->recs, v->tl) != v->tables_crc) return CKPT_ECORRUPT;
+        // kinds and payload length
+        uint64_t dsum = 0;
+        const bool delta = v->flags & 1u;
+        for (uint64_t a = 0, gg = 0; a < v->n_allocs; ++a) {
+            const uint64_t size = get64(v->recs + 32 * a + 8), nk = ceil_div(size, v->C);
+            for (uint64_t k = 0; k < nk; ++k, ++gg) {
+                const uint8_t kd = v->kinds[gg];
+                if (kd > kUnchanged || (kd == kUnchanged && !delta)) return CKPT_ECORRUPT;
+                if (kd == kData) dsum += round16(k + 1 == nk ? size - k * v->C : v->C);
+            }
+        }
+        if (dsum != v->D) return CKPT_ECORRUPT;
+        v->state_digest = host_crc32c(v->recs, 32ull * v->n_allocs + 4 * v->n_chunks);
+    }
+    return CKPT_OK;
+}
+
+}  // namespace mk
+
+// ------------------------------------------------------------ device buffers
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    uint64_t cap = 0;
+    hipError_t ensure(uint64_t n) {
+        if (n <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        uint64_t want = std::max<uint64_t>(n, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) return e;
+        cap = want;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// A resident digest table of an image: its crc[] on the device, kept for
+// later delta dumps taken against that image.
+struct DigestEntry {
+    DevBuf crc;
+    uint64_t n_chunks = 0;
+    uint64_t last_use = 0;
+};
+
+}  // namespace
+
+struct ckpt_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    int num_cu = 0;
+    hipStream_t s_main = nullptr;
+    std::vector<hipStream_t> s_copy;
+    std::mutex mu;
+    uint32_t epoch = 0;
+    uint64_t use_clock = 0;
+    // device buffers
+    DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig;
+    std::map<std::pair<int, uint32_t>, DevBuf> consts;    // (T, C) -> EngineConsts
+    std::map<std::tuple<int, int, int>, int> occ;          // (T, K, mode) -> blocks per CU
+    std::unordered_map<uint64_t, DigestEntry> digests;    // image uid -> resident crc[]
+    // pinned host scratch for small transfers
+    uint8_t* hsmall = nullptr;
+    uint64_t hsmall_cap = 0;
+    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> tevents;                      // timing events (begin, end) per launch
+};
+
+// ------------------------------------------------------------ helpers
+namespace {
+
+#define HIPCHK(call)                                 \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) {                      \
+            if (res) res->hip_error = (int32_t)e_;   \
+            return CKPT_EHIP;                        \
+        }                                            \
+    } while (0)
+
+uint32_t next_epoch(ckpt_ctx* c, bool* wrapped) {
+    *wrapped = false;
+    if (++c->epoch > kEpochMask) {
+        c->epoch = 1;
+        *wrapped = true;
+    }
+    return c->epoch;
+}
+
+// Tile shape for a chunk size: threads T and rows K per pass (16 T K <= C).
+void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K) {
+    if (C <= 512) { *T = (int)(C / 16); *K = 1; return; }
+    static const int shapes[][2] = {{1024, 8}, {512, 8}, {1024, 4}, {256, 8}, {512, 4}, {256, 4},
+                                    {64, 4}, {256, 1}, {64, 1}};
+    static const int prefer[][3] = {   // C, T, K defaults
+        {1 << 10, 64, 1}, {2 << 10, 64, 1}, {4 << 10, 64, 4}, {8 << 10, 64, 4}, {16 << 10, 256, 4},
+        {32 << 10, 256, 8}, {64 << 10, 512, 8}, {128 << 10, 1024, 8}};
+    if (want_t) {
+        for (auto& s : shapes)
+            if ((uint32_t)s[0] == want_t && 16u * s[0] * s[1] <= C) { *T = s[0]; *K = s[1]; return; }
+    }
+    for (auto& p : prefer)
+        if ((uint32_t)p[0] == C) { *T = p[1]; *K = p[2]; return; }
+    *T = 1024; *K = 8;   // larger chunks: several passes of 128 KiB
+}
+
+hipError_t get_consts(ckpt_ctx* c, int T, uint32_t C, const EngineConsts** out) {
+    auto key = std::make_pair(T, C);
+    auto it = c->consts.find(key);
+    if (it == c->consts.end()) {
+        EngineConsts* h = new EngineConsts();
+        build_engine_consts(h, T, C);
+        DevBuf b;
+        hipError_t e = b.ensure(sizeof(EngineConsts));
+        if (e == hipSuccess) e = hipMemcpy(b.p, h, sizeof(EngineConsts), hipMemcpyHostToDevice);
+        delete h;
+        if (e != hipSuccess) { b.release(); return e; }
+        it = c->consts.emplace(key, b).first;
+    }
+    *out = it->second.as<EngineConsts>();
+    return hipSuccess;
+}
+
+hipError_t grid_for(ckpt_ctx* c, int T, int K, int mode, uint64_t work, int* grid) {
+    auto key = std::make_tuple(T, K, mode);
+    auto it = c->occ.find(key);
+    if (it == c->occ.end()) {
+        int n = 0;
+        hipError_t e = chunks_occupancy(T, K, mode, &n);
+        if (e != hipSuccess) return e;
+        it = c->occ.emplace(key, std::max(1, n)).first;
+    }
+    uint64_t g = (uint64_t)it->second * (uint64_t)c->num_cu;
+    *grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(g, work));
+    return hipSuccess;
+}
+
+hipError_t ensure_hsmall(ckpt_ctx* c, uint64_t n) {
+    if (n <= c->hsmall_cap) return hipSuccess;
+    if (c->hsmall) hipHostFree(c->hsmall);
+    c->hsmall = nullptr;
+    c->hsmall_cap = 0;
+    hipError_t e = hipHostMalloc((void**)&c->hsmall, n, hipHostMallocDefault);
+    if (e == hipSuccess) c->hsmall_cap = n;
+    return e;
+}
+
+hipError_t ensure_tevents(ckpt_ctx* c, size_t n) {
+    while (c->tevents.size() < n) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->tevents.push_back(e);
+    }
+    return hipSuccess;
+}
+
+// Summed device time of the launches bracketed by timing events [0, 2n).
+uint64_t timed_ns(ckpt_ctx* c, size_t n) {
+    double total = 0;
+    for (size_t i = 0; i < n; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->tevents[2 * i], c->tevents[2 * i + 1]) == hipSuccess) total += ms;
+    }
+    return (uint64_t)(total * 1e6);
+}
+
+hipError_t ensure_events(ckpt_ctx* c, size_t n) {
+    while (c->events.size() < n) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        c->events.push_back(e);
+    }
+    return hipSuccess;
+}
+
+// Descriptor of one allocation for chunk size C.
+void make_desc(AllocDesc* d, uint64_t id, const void* ptr, uint64_t size, uint64_t first, uint64_t prev_first,
+               uint32_t C) {
+    memset(d, 0, sizeof(*d));
+    d->ptr = reinterpret_cast<uint64_t>(ptr);
+    d->size = size;
+    d->first = first;
+    d->prev_first = prev_first;
+    d->id = id;
+    if (size) {
+        const uint64_t nk = ceil_div(size, C);
+        const uint32_t tail = (uint32_t)(size - (nk - 1) * C);
+        d->tail_len = tail;
+        d->tail_x = xpow8(tail);
+        d->tail_init = gf_mul(0xFFFFFFFFu, d->tail_x);
+        d->tail_unshift = xinvpow8(C - tail);
+    }
+}
+
+struct Window {
+    uint64_t g0, g1;
+};
+
+// Staging windows: whole chunks, at most `slot` bytes of payload each.
+std::vector<Window> plan_windows(const std::vector<AllocDesc>& d, uint64_t n_chunks, uint32_t C, uint64_t slot,
+                                 bool per_alloc) {
+    std::vector<Window> w;
+    const uint64_t per = std::max<uint64_t>(1, slot / C);
+    if (!per_alloc) {
+        for (uint64_t g = 0; g < n_chunks; g += per) w.push_back({g, std::min(n_chunks, g + per)});
+        return w;
+    }
+    for (const AllocDesc& a : d) {
+        const uint64_t nk = ceil_div(a.size, C);
+        for (uint64_t k = 0; k < nk; k += per) w.push_back({a.first + k, a.first + std::min(nk, k + per)});
+    }
+    return w;
+}
+
+void fill_result(ckpt_result* res) {
+    if (!res) return;
+    memset(res, 0, sizeof(*res));
+    res->first_bad_chunk = kNoChunk;
+}
+
+// Make the context's main stream wait for prior work on the caller's stream.
+hipError_t order_after(ckpt_ctx* c, void* stream) {
+    if (ensure_events(c, 1) != hipSuccess) return hipErrorOutOfMemory;
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->s_main, ev, 0);
+    hipEventDestroy(ev);
+    return e;
+}
+
+// Staging geometry. Windows are ranges of whole chunks, floor(slot / C)
+// chunks each, so a window's payload never exceeds its slot. One slot when
+// everything fits in one window; otherwise at least two, so the next
+// window's kernel can run while the previous window is copied out.
+void pick_staging(const ckpt_ctx* c, const ckpt_opts* o, uint64_t n_chunks, uint32_t C, uint64_t* slot,
+                  int* nslots) {
+    const uint64_t budget = c->budget;
+    const uint64_t all = std::max<uint64_t>(n_chunks, 1) * C;   // one window for every chunk
+    if (o && o->window_bytes) {
+        *slot = std::max<uint64_t>(o->window_bytes, C);
+    } else if (all <= std::min<uint64_t>(budget, 1ull << 30)) {
+        *slot = all;
+    } else {
+        *slot = std::min<uint64_t>(budget / 3, 2ull << 30);
+        *slot = std::max<uint64_t>(*slot, std::max<uint64_t>(C, 64ull << 20));
+    }
+    *slot = *slot / C * C;
+    const uint64_t windows = ceil_div(std::max<uint64_t>(n_chunks, 1), *slot / C);
+    int s = (o && o->slots) ? (int)o->slots : 3;
+    if (windows == 1) s = 1;
+    while (s > 2 && (uint64_t)s * *slot > budget) --s;
+    if (windows > 1 && s < 2) s = 2;
+    *nslots = s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ context API
+extern "C" int ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** out) {
+    if (!out) return CKPT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CKPT_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return CKPT_EHIP;
+    ckpt_ctx* c = new ckpt_ctx();
+    c->device = device;
+    c->budget = staging_budget ? staging_budget : kDefaultBudget;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return CKPT_EHIP; }
+    c->num_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->s_main, hipStreamNonBlocking) != hipSuccess) { delete c; return CKPT_EHIP; }
+    *out = c;
+    return CKPT_OK;
+}
+
+static hipError_t ensure_copy_streams(ckpt_ctx* c, uint32_t n) {
+    while (c->s_copy.size() < n) {
+        hipStream_t s;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        c->s_copy.push_back(s);
+    }
+    return hipSuccess;
+}
+
+extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->s_main);
+    for (hipStream_t s : c->s_copy) { hipStreamSynchronize(s); hipStreamDestroy(s); }
+    hipStreamDestroy(c->s_main);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    for (hipEvent_t e : c->tevents) hipEventDestroy(e);
+    DevBuf* bufs[] = {&c->descs, &c->status, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
+                      &c->staging, &c->dig};
+    for (DevBuf* b : bufs) b->release();
+    for (auto& kv : c->consts) kv.second.release();
+    for (auto& kv : c->digests) kv.second.crc.release();
+    if (c->hsmall) hipHostFree(c->hsmall);
+    delete c;
+}
+
+// ------------------------------------------------------------ table digests
+// CRC of [AllocRec || crc] (the state digest) and of [kinds || pad] on the
+// device, via the chunk engine in digest mode over two virtual allocations
+// followed by the per-allocation combine.
+static int device_table_digests(ckpt_ctx* c, const uint8_t* recs_crc, uint64_t len_a, const uint8_t* kinds_pad,
+                                uint64_t len_b, uint32_t* out_host /* [2], pinned */, ckpt_result* res) {
+    const uint32_t Cd = 16384;
+    int T, K;
+    pick_tile(Cd, 0, &T, &K);
+    const EngineConsts* ec;
+    HIPCHK(get_consts(c, T, Cd, &ec));
+    AllocDesc hd[2];
+    const uint64_t nk_a = ceil_div(len_a, Cd), nk_b = ceil_div(len_b, Cd);
+    make_desc(&hd[0], 0, recs_crc, len_a, 0, kNoChunk, Cd);
+    make_desc(&hd[1], 1, kinds_pad, len_b, nk_a, kNoChunk, Cd);
+    const uint64_t nk = nk_a + nk_b;
+    // dig buffer: [2 descs][crc of nk chunks][2 outputs][ticket]
+    const uint64_t off_crc = 128, off_out = off_crc + 4 * std::max<uint64_t>(nk, 1), off_tk = off_out + 16;
+    HIPCHK(c->dig.ensure(off_tk + 64));
+    uint8_t* base = c->dig.as<uint8_t>();
+    HIPCHK(hipMemcpyAsync(base, hd, sizeof(hd), hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(base + off_tk), 0, 1, c->s_main));
+    if (nk) {
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = reinterpret_cast<const AllocDesc*>(base);
+        j.n_allocs = 2;
+        j.C = Cd;
+        j.g0 = 0;
+        j.g1 = nk;
+        j.ec = ec;
+        j.crc_out = reinterpret_cast<uint32_t*>(base + off_crc);
+        j.ticket = reinterpret_cast<uint32_t*>(base + off_tk);
+        int grid;
+        HIPCHK(grid_for(c, T, K, kModeDigest, nk, &grid));
+        HIPCHK(launch_chunks(T, K, kModeDigest, j, grid, c->s_main));
+    }
+    CombineJob cj;
+    memset(&cj, 0, sizeof(cj));
+    cj.allocs = reinterpret_cast<const AllocDesc*>(base);
+    cj.n_allocs = 2;
+    cj.C = Cd;
+    cj.crc = reinterpret_cast<const uint32_t*>(base + off_crc);
+    cj.ec = ec;
+    cj.out = reinterpret_cast<uint32_t*>(base + off_out);
+    cj.mode = kCombineOut;
+    HIPCHK(launch_combine(cj, c->s_main));
+    HIPCHK(hipMemcpyAsync(out_host, base + off_out, 8, hipMemcpyDeviceToHost, c->s_main));
+    return CKPT_OK;
+}
+
+// ------------------------------------------------------------ dump
+static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+                     const ckpt_opts* o, void* stream, ckpt_result* res) {
+    const uint64_t t_start = now_ns();
+    const uint32_t C = (o && o->chunk_size) ? o->chunk_size : kDefaultChunk;
+    if (!valid_chunk(C)) return CKPT_EINVAL;
+    if (o && (o->reserved || (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING))))
+        return CKPT_EINVAL;
+    const uint32_t n = table->n;
+    if (n && !table->v) return CKPT_EINVAL;
+    {
+        std::unordered_set<uint64_t> ids;
+        ids.reserve(n * 2 + 1);
+        for (uint32_t a = 0; a < n; ++a) {
+            const ckpt_alloc& e = table->v[a];
+            if (!ids.insert(e.id).second) return CKPT_EINVAL;
+            if (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15))) return CKPT_EINVAL;
+        }
+    }
+    // previous image
+    ImageView pv;
+    std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> prev_map;   // id -> (size, first)
+    if (prev) {
+        int rc = parse_image(prev->p, prev->n, &pv, false);
+        if (rc) return rc;
+        if (pv.C != C) return CKPT_EINVAL;
+        pv.state_digest = host_crc32c(pv.recs, 32ull * pv.n_allocs + 4 * pv.n_chunks);
+        prev_map.reserve(pv.n_allocs * 2 + 1);
+        for (uint64_t a = 0; a < pv.n_allocs; ++a)
+            prev_map.emplace(get64(pv.recs + 32 * a), std::make_pair(get64(pv.recs + 32 * a + 8),
+                                                                     get64(pv.recs + 32 * a + 16)));
+    }
+    // descriptors
+    std::vector<AllocDesc> d(n);
+    uint64_t g = 0, N = 0, upper = 0;
+    for (uint32_t a = 0; a < n; ++a) {
+        const ckpt_alloc& e = table->v[a];
+        uint64_t pf = kNoChunk;
+        if (prev) {
+            auto it = prev_map.find(e.id);
+            if (it != prev_map.end() && it->second.first == e.size) pf = it->second.second;
+        }
+        make_desc(&d[a], e.id, e.dev_ptr, e.size, g, pf, C);
+        const uint64_t nk = ceil_div(e.size, C);
+        g += nk;
+        N += e.size;
+        if (nk) upper += (nk - 1) * C + round16(d[a].tail_len);
+    }
+    const uint64_t nc = g;
+    const uint64_t tl = tables_len(n, nc);
+    const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
+    int T, K;
+    pick_tile(C, o ? o->wg_threads : 0, &T, &K);
+    uint64_t slot;
+    int nslots;
+    pick_staging(c, o, nc, C, &slot, &nslots);
+    std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
+    const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
+    if ((uint64_t)nslots * slot > c->budget && nslots > 1) return CKPT_ENOMEM;
+
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(ensure_copy_streams(c, ncs));
+    HIPCHK(order_after(c, stream));
+    // device buffers
+    HIPCHK(c->descs.ensure(sizeof(AllocDesc) * std::max<uint32_t>(n, 1)));
+    HIPCHK(c->arc.ensure(tl + 16));
+    HIPCHK(c->kinds.ensure(tl + 16));
+    HIPCHK(c->staging.ensure((uint64_t)nslots * slot));
+    uint64_t max_win = 1;
+    for (const Window& w : wins) max_win = std::max(max_win, w.g1 - w.g0);
+    HIPCHK(c->status.ensure(8 * (max_win + 64)));
+    const uint64_t W = wins.size();
+    // ctl: tickets[W] | wtot[W] (u64) | err
+    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (W + 1)), ctl_err = ctl_wt + 8 * (W + 1);
+    HIPCHK(c->ctl.ensure(ctl_err + 64));
+    HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
+    HIPCHK(ensure_events(c, W + (size_t)nslots + 2));
+    const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * W));
+    const EngineConsts* ec;
+    HIPCHK(get_consts(c, T, C, &ec));
+
+    // resident digest table of the previous image
+    const uint32_t* prev_dev = nullptr;
+    if (prev && pv.n_chunks) {
+        auto it = c->digests.find(prev->uid);
+        if (it != c->digests.end() && it->second.n_chunks == pv.n_chunks) {
+            prev_dev = it->second.crc.as<uint32_t>();
+            it->second.last_use = ++c->use_clock;
+        } else {
+            HIPCHK(c->prevcrc.ensure(4 * pv.n_chunks));
+            HIPCHK(hipMemcpyAsync(c->prevcrc.p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, c->s_main));
+            prev_dev = c->prevcrc.as<uint32_t>();
+        }
+    }
+
+    uint8_t* ctl = c->ctl.as<uint8_t>();
+    uint32_t* tickets = reinterpret_cast<uint32_t*>(ctl + ctl_tk);
+    uint64_t* wtot = reinterpret_cast<uint64_t*>(ctl + ctl_wt);
+    uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
+    HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (ctl_err + 64) / 4, c->s_main));
+    // kinds buffer: zero padding after the kinds (the kinds themselves are written by the kernel)
+    HIPCHK(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
+
+    // image buffer
+    ckpt_image* im = image_new(kHeader + tl + upper);
+    if (!im) return CKPT_ENOMEM;
+    uint8_t* himg = im->p;
+    uint64_t* hw = reinterpret_cast<uint64_t*>(c->hsmall);
+    uint32_t* crc_dev = reinterpret_cast<uint32_t*>(c->arc.as<uint8_t>() + 32ull * n);
+    uint8_t* kind_dev = c->kinds.as<uint8_t>();
+    std::vector<hipEvent_t>& ev = c->events;   // [0, W): window done; [W, W+nslots): slot free
+    std::vector<bool> slot_used(nslots, false);
+    auto fail = [&](hipError_t e) {
+        hipStreamSynchronize(c->s_main);
+        for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
+        pool().put(im->p, im->cap);
+        delete im;
+        if (res) res->hip_error = (int32_t)e;
+        return CKPT_EHIP;
+    };
+
+    auto launch_window = [&](uint64_t w) -> hipError_t {
+        const int s = (int)(w % nslots);
+        hipError_t e;
+        if (slot_used[s]) {
+            e = hipStreamWaitEvent(c->s_main, ev[W + s], 0);
+            if (e != hipSuccess) return e;
+        }
+        slot_used[s] = true;
+        bool wrapped;
+        const uint32_t ep = next_epoch(c, &wrapped);
+        if (wrapped) {
+            e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main);
+            if (e != hipSuccess) return e;
+        }
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = c->descs.as<AllocDesc>();
+        j.n_allocs = n;
+        j.C = C;
+        j.g0 = wins[w].g0;
+        j.g1 = wins[w].g1;
+        j.ec = ec;
+        j.crc_out = crc_dev;
+        j.kind_out = kind_dev;
+        j.prev_crc = prev_dev;
+        j.slot = c->staging.as<uint8_t>() + (uint64_t)s * slot;
+        j.status = c->status.as<uint64_t>();
+        j.ticket = tickets + w;
+        j.wtotal = wtot + w;
+        j.err = err;
+        j.epoch = ep;
+        int grid;
+        e = grid_for(c, T, K, kModeDump, j.g1 - j.g0, &grid);
+        if (e != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[2 * w], c->s_main)) != hipSuccess) return e;
+        e = launch_chunks(T, K, kModeDump, j, grid, c->s_main);
+        if (e != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[2 * w + 1], c->s_main)) != hipSuccess) return e;
+        e = hipMemcpyAsync(hw + w, wtot + w, 8, hipMemcpyDeviceToHost, c->s_main);
+        if (e != hipSuccess) return e;
+        return hipEventRecord(ev[w], c->s_main);
+    };
+
+    uint64_t pos = 0, t_link0 = 0;
+    hipError_t e = hipSuccess;
+    // Window w+1 is launched before window w is copied out only when it has
+    // a slot of its own (nslots >= 2): its slot-free event then belongs to
+    // a copy that has already been issued.
+    const bool ahead = nslots >= 2;
+    if (W) e = launch_window(0);
+    for (uint64_t w = 0; w < W && e == hipSuccess; ++w) {
+        if (w > 0 && !ahead) {
+            e = launch_window(w);
+            if (e != hipSuccess) break;
+        }
+        if (ahead && w + 1 < W) {
+            e = launch_window(w + 1);
+            if (e != hipSuccess) break;
+        }
+        e = hipEventSynchronize(ev[w]);
+        if (e != hipSuccess) break;
+        const uint64_t dw = hw[w];
+        if (dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
+        const int s = (int)(w % nslots);
+        hipStream_t cs = c->s_copy[w % ncs];
+        if (!t_link0) t_link0 = now_ns();
+        // device-side dependency on the window's kernel: the host wait above
+        // gives the payload length, but only a stream dependency orders the
+        // copy engine's reads after the kernel's stores
+        e = hipStreamWaitEvent(cs, ev[w], 0);
+        if (e != hipSuccess) break;
+        if (dw) {
+            e = hipMemcpyAsync(himg + kHeader + tl + pos, c->staging.as<uint8_t>() + (uint64_t)s * slot, dw,
+                               hipMemcpyDeviceToHost, cs);
+            if (e != hipSuccess) break;
+        }
+        e = hipEventRecord(ev[W + s], cs);
+        pos += dw;
+    }
+    if (e != hipSuccess) return fail(e);
+    const uint64_t D = pos;
+
+    // per-allocation CRCs -> AllocRec[] (in the device arc buffer)
+    CombineJob cj;
+    memset(&cj, 0, sizeof(cj));
+    cj.allocs = c->descs.as<AllocDesc>();
+    cj.n_allocs = n;
+    cj.C = C;
+    cj.crc = crc_dev;
+    cj.ec = ec;
+    cj.recs = c->arc.as<uint8_t>();
+    cj.mode = kCombineWrite;
+    if ((e = launch_combine(cj, c->s_main)) != hipSuccess) return fail(e);
+    // table digests
+    const uint64_t len_a = 32ull * n + 4 * nc, len_b = tl - len_a;
+    uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall + 8 * (W + 1));
+    int rc = device_table_digests(c, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, hdig, res);
+    if (rc) return fail(hipErrorUnknown);
+    // tables into the image
+    if ((e = hipMemcpyAsync(himg + kHeader, c->arc.p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpyAsync(himg + kHeader + len_a, kind_dev, len_b, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpyAsync(hdig + 2, err, 4, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
+    for (uint32_t i = 0; i < ncs; ++i)
+        if ((e = hipStreamSynchronize(c->s_copy[i])) != hipSuccess) return fail(e);
+    const uint64_t t_link1 = now_ns();
+    if (hdig[2] != 0) return fail(hipErrorLaunchTimeOut);
+
+    // header
+    const uint32_t sd = hdig[0];
+    const uint32_t tcrc = crc_combine(sd, hdig[1], len_b);
+    uint8_t* h = himg;
+    memcpy(h, "MICKPT01", 8);
+    put32(h + 8, 1);
+    put32(h + 12, prev ? 1u : 0u);
+    put32(h + 16, C);
+    put32(h + 20, n);
+    put64(h + 24, nc);
+    put64(h + 32, D);
+    put32(h + 40, prev ? pv.state_digest : 0u);
+    put32(h + 44, 0);
+    put64(h + 48, N);
+    put32(h + 56, tcrc);
+    put32(h + 60, host_crc32c(h, 60));
+    im->n = kHeader + tl + D;
+
+    // keep this image's digest table resident for later delta dumps
+    if (nc) {
+        const size_t kMaxEntries = 8;
+        if (c->digests.size() >= kMaxEntries) {
+            auto victim = c->digests.begin();
+            for (auto it = c->digests.begin(); it != c->digests.end(); ++it)
+                if (it->second.last_use < victim->second.last_use) victim = it;
+            victim->second.crc.release();
+            c->digests.erase(victim);
+        }
+        DigestEntry& de = c->digests[im->uid];
+        if (de.crc.ensure(4 * nc) == hipSuccess &&
+            hipMemcpyAsync(de.crc.p, crc_dev, 4 * nc, hipMemcpyDeviceToDevice, c->s_main) == hipSuccess &&
+            hipStreamSynchronize(c->s_main) == hipSuccess) {
+            de.n_chunks = nc;
+            de.last_use = ++c->use_clock;
+        } else {
+            de.crc.release();
+            c->digests.erase(im->uid);
+        }
+    }
+    if (res) {
+        res->windows = (uint32_t)W;
+        res->n_logical = N;
+        res->n_payload = D;
+        res->n_chunks = nc;
+        res->link_bytes = D + tl + kHeader;
+        res->ns_link = t_link0 ? t_link1 - t_link0 : 0;
+        res->ns_kernel = timing ? timed_ns(c, W) : 0;
+        res->ns_total = now_ns() - t_start;
+        const uint8_t* kinds = himg + kHeader + 32ull * n + 4 * nc;
+        for (uint64_t i = 0; i < nc; ++i) {
+            if (kinds[i] == kZero) ++res->n_zero;
+            else if (kinds[i] == kData) ++res->n_data;
+            else ++res->n_unchanged;
+        }
+    }
+    *out = im;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+                         const ckpt_opts* o, void* stream, ckpt_result* res) {
+    fill_result(res);
+    if (!out) return CKPT_EINVAL;
+    *out = nullptr;
+    if (!c || !table) return CKPT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    return dump_impl(c, table, prev, out, o, stream, res);
+}
+
+// ------------------------------------------------------------ restore
+static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                        void* stream, ckpt_result* res) {
+    const uint64_t t_start = now_ns();
+    if (o && (o->reserved || (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING))))
+        return CKPT_EINVAL;
+    const uint32_t n = table->n;
+    if (n && !table->v) return CKPT_EINVAL;
+    ImageView v;
+    int rc = parse_image(img->p, img->n, &v, false);   // header and structure; tables digest on the device
+    if (rc) return rc;
+    const uint32_t C = v.C;
+    const uint64_t nc = v.n_chunks, tl = v.tl;
+    const uint64_t len_a = 32ull * v.n_allocs + 4 * nc, len_b = tl - len_a;
+    for (uint32_t a = 0; a < n && a < v.n_allocs; ++a) {
+        const ckpt_alloc& e = table->v[a];
+        if (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15))) return CKPT_EINVAL;
+    }
+    // descriptors from the image's records (sizes, grid) and the caller's pointers
+    std::vector<AllocDesc> d(v.n_allocs);
+    uint64_t upper = 0;
+    for (uint64_t a = 0; a < v.n_allocs; ++a) {
+        const uint8_t* r = v.recs + 32 * a;
+        const void* ptr = a < n ? table->v[a].dev_ptr : nullptr;
+        make_desc(&d[a], get64(r), ptr, get64(r + 8), get64(r + 16), kNoChunk, C);
+        const uint64_t nk = ceil_div(d[a].size, C);
+        if (nk) upper += (nk - 1) * C + round16(d[a].tail_len);
+    }
+    const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
+    int T, K;
+    pick_tile(C, o ? o->wg_threads : 0, &T, &K);
+    uint64_t slot;
+    int nslots;
+    pick_staging(c, o, nc, C, &slot, &nslots);
+    std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
+    const uint64_t W = wins.size();
+    const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
+
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(ensure_copy_streams(c, ncs));
+    HIPCHK(order_after(c, stream));
+    HIPCHK(c->descs.ensure(sizeof(AllocDesc) * std::max<uint64_t>(v.n_allocs, 1)));
+    HIPCHK(c->arc.ensure(tl + 16));
+    HIPCHK(c->kinds.ensure(tl + 16));
+    HIPCHK(c->off.ensure(8 * std::max<uint64_t>(nc, 1)));
+    HIPCHK(c->wb.ensure(8 * (W + 2)));
+    HIPCHK(c->staging.ensure((uint64_t)nslots * slot));
+    HIPCHK(c->status.ensure(8 * (ceil_div(nc, 256) + 64)));
+    // ctl: ticket[1] | counts[4] u64 | bad u64 | bad2 u64 | err | window tickets[W]
+    const uint64_t ctl_cnt = 64, ctl_bad = ctl_cnt + 32, ctl_bad2 = ctl_bad + 8, ctl_err = ctl_bad2 + 8,
+                   ctl_wtk = ctl_err + 8;
+    HIPCHK(c->ctl.ensure(ctl_wtk + 4 * (W + 2) + 64));
+    HIPCHK(ensure_hsmall(c, 8 * (W + 2) + 128));
+    HIPCHK(ensure_events(c, 2 * W + (size_t)nslots + 2));
+    const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * W));
+    const EngineConsts* ec;
+    HIPCHK(get_consts(c, T, C, &ec));
+    uint8_t* ctl = c->ctl.as<uint8_t>();
+    uint32_t* ticket = reinterpret_cast<uint32_t*>(ctl);
+    unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctl + ctl_cnt);
+    unsigned long long* bad = reinterpret_cast<unsigned long long*>(ctl + ctl_bad);
+    unsigned long long* bad2 = reinterpret_cast<unsigned long long*>(ctl + ctl_bad2);
+    uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
+    uint32_t* wtk = reinterpret_cast<uint32_t*>(ctl + ctl_wtk);
+    uint32_t* crc_dev = reinterpret_cast<uint32_t*>(c->arc.as<uint8_t>() + 32ull * v.n_allocs);
+    uint8_t* kind_dev = c->kinds.as<uint8_t>();
+
+    // 1) tables up, their digest, payload offsets
+    HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * d.size(), hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(hipMemcpyAsync(c->arc.p, v.recs, len_a, hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(hipMemcpyAsync(kind_dev, v.kinds, len_b, hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, ctl_bad / 4, c->s_main));
+    HIPCHK(launch_fill64(reinterpret_cast<uint64_t*>(bad), ~0ull, 2, c->s_main));
+    HIPCHK(launch_fill32(err, 0, 2 + W + 2, c->s_main));
+    uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall);
+    uint64_t* hq = reinterpret_cast<uint64_t*>(c->hsmall + 64);   // counts[4], bad, bad2, err
+    uint64_t* hwb = reinterpret_cast<uint64_t*>(c->hsmall + 128);
+    rc = device_table_digests(c, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, hdig, res);
+    if (rc) return rc;
+    if (nc) {
+        bool wrapped;
+        const uint32_t ep = next_epoch(c, &wrapped);
+        if (wrapped) HIPCHK(launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main));
+        OffJob oj;
+        memset(&oj, 0, sizeof(oj));
+        oj.allocs = c->descs.as<AllocDesc>();
+        oj.n_allocs = v.n_allocs;
+        oj.C = C;
+        oj.n_chunks = nc;
+        oj.kind = kind_dev;
+        oj.off = c->off.as<uint64_t>();
+        // fixed-size windows take their payload boundaries from the scan;
+        // per-allocation windows compute them on the host below
+        oj.per_window = per_alloc ? nc + 1 : std::max<uint64_t>(1, slot / C);
+        oj.wb = c->wb.as<uint64_t>();
+        oj.n_windows = per_alloc ? 1 : W;
+        oj.status = c->status.as<uint64_t>();
+        oj.ticket = ticket;
+        oj.counts = counts;
+        oj.err = err;
+        oj.epoch = ep;
+        const uint64_t tiles = ceil_div(nc, 256);
+        HIPCHK(launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main));
+    }
+    HIPCHK(hipMemcpyAsync(hq, counts, 32, hipMemcpyDeviceToHost, c->s_main));
+    HIPCHK(hipStreamSynchronize(c->s_main));
+    // validation in the oracle's order: tables digest and structure, then the match
+    if (crc_combine(hdig[0], hdig[1], len_b) != v.tables_crc) return CKPT_ECORRUPT;
+    const uint64_t nz = hq[0], nd = hq[1], nu = hq[2], ninv = hq[3];
+    if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != nc) return CKPT_ECORRUPT;
+    // window offsets: payload total must equal D
+    std::vector<uint64_t> wbh;
+    if (nc) {
+        if (per_alloc) {
+            wbh.assign(W + 1, 0);
+            uint64_t acc = 0, w = 0;
+            for (uint64_t a = 0; a < v.n_allocs; ++a) {
+                const uint64_t nk = ceil_div(d[a].size, C);
+                for (uint64_t k = 0; k < nk; ++k) {
+                    const uint64_t gg = d[a].first + k;
+                    while (w < W && wins[w].g0 == gg) wbh[w++] = acc;
+                    if (v.kinds[gg] == kData) acc += round16(k + 1 == nk ? d[a].tail_len : C);
+                }
+            }
+            wbh[W] = acc;
+        } else {
+            HIPCHK(hipMemcpy(hwb, c->wb.p, 8 * (W + 1), hipMemcpyDeviceToHost));
+            wbh.assign(hwb, hwb + W + 1);
+        }
+        if (wbh[W] != v.D) return CKPT_ECORRUPT;
+    } else if (v.D != 0) {
+        return CKPT_ECORRUPT;
+    }
+    if (v.n_allocs != n) return CKPT_EMISMATCH;
+    for (uint32_t a = 0; a < n; ++a)
+        if (table->v[a].id != d[a].id || table->v[a].size != d[a].size) return CKPT_EMISMATCH;
+
+    // 2) a delta needs its base in place
+    if (nu) {
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = c->descs.as<AllocDesc>();
+        j.n_allocs = n;
+        j.C = C;
+        j.g0 = 0;
+        j.g1 = nc;
+        j.ec = ec;
+        j.kind_in = kind_dev;
+        j.ref_crc = crc_dev;
+        j.ticket = wtk + W;
+        j.bad = bad;
+        j.err = err;
+        int grid;
+        HIPCHK(grid_for(c, T, K, kModeVerify, nc, &grid));
+        HIPCHK(launch_chunks(T, K, kModeVerify, j, grid, c->s_main));
+        HIPCHK(hipMemcpyAsync(hq + 4, bad, 8, hipMemcpyDeviceToHost, c->s_main));
+        HIPCHK(hipStreamSynchronize(c->s_main));
+        if (hq[4] != kNoChunk) {
+            if (res) res->first_bad_chunk = hq[4];
+            return CKPT_EBASE;
+        }
+    }
+
+    // 3) windows: payload slice up, scatter + verify
+    std::vector<hipEvent_t>& ev = c->events;   // [0,W): copied; [W, W+nslots): slot free
+    std::vector<bool> slot_used(nslots, false);
+    const uint64_t t_link0 = now_ns();
+    for (uint64_t w = 0; w < W; ++w) {
+        const int s = (int)(w % nslots);
+        hipStream_t cs = c->s_copy[w % ncs];
+        uint8_t* sp = c->staging.as<uint8_t>() + (uint64_t)s * slot;
+        if (slot_used[s]) HIPCHK(hipStreamWaitEvent(cs, ev[W + s], 0));
+        slot_used[s] = true;
+        const uint64_t len = wbh[w + 1] - wbh[w];
+        if (len > slot) return CKPT_ECORRUPT;
+        if (len) HIPCHK(hipMemcpyAsync(sp, v.payload + wbh[w], len, hipMemcpyHostToDevice, cs));
+        HIPCHK(hipEventRecord(ev[w], cs));
+        HIPCHK(hipStreamWaitEvent(c->s_main, ev[w], 0));
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = c->descs.as<AllocDesc>();
+        j.n_allocs = n;
+        j.C = C;
+        j.g0 = wins[w].g0;
+        j.g1 = wins[w].g1;
+        j.ec = ec;
+        j.kind_in = kind_dev;
+        j.ref_crc = crc_dev;
+        j.slot = sp;
+        j.off = c->off.as<uint64_t>();
+        j.slot_base = wbh[w];
+        j.ticket = wtk + w;
+        j.bad = bad;
+        j.err = err;
+        int grid;
+        HIPCHK(grid_for(c, T, K, kModeRestore, j.g1 - j.g0, &grid));
+        if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w], c->s_main));
+        HIPCHK(launch_chunks(T, K, kModeRestore, j, grid, c->s_main));
+        if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w + 1], c->s_main));
+        HIPCHK(hipEventRecord(ev[W + s], c->s_main));
+    }
+    // 4) whole-allocation CRCs
+    CombineJob cj;
+    memset(&cj, 0, sizeof(cj));
+    cj.allocs = c->descs.as<AllocDesc>();
+    cj.n_allocs = n;
+    cj.C = C;
+    cj.crc = crc_dev;
+    cj.ec = ec;
+    cj.recs = c->arc.as<uint8_t>();
+    cj.bad = bad2;
+    cj.mode = kCombineCheck;
+    HIPCHK(launch_combine(cj, c->s_main));
+    HIPCHK(hipMemcpyAsync(hq + 4, bad, 24, hipMemcpyDeviceToHost, c->s_main));
+    HIPCHK(hipStreamSynchronize(c->s_main));
+    for (uint32_t i = 0; i < ncs; ++i) HIPCHK(hipStreamSynchronize(c->s_copy[i]));
+    const uint64_t t_link1 = now_ns();
+    if ((uint32_t)hq[6] != 0) {
+        if (res) res->hip_error = (int32_t)hipErrorLaunchTimeOut;
+        return CKPT_EHIP;
+    }
+    if (res) {
+        res->windows = (uint32_t)W;
+        res->n_logical = v.N;
+        res->n_payload = v.D;
+        res->n_chunks = nc;
+        res->n_zero = nz;
+        res->n_data = nd;
+        res->n_unchanged = nu;
+        res->link_bytes = v.D + tl + kHeader;
+        res->ns_link = t_link1 - t_link0;
+        res->ns_kernel = timing ? timed_ns(c, W) : 0;
+        res->ns_total = now_ns() - t_start;
+    }
+    if (hq[4] != kNoChunk) {
+        if (res) res->first_bad_chunk = hq[4];
+        return CKPT_ECORRUPT;
+    }
+    if (hq[5] != kNoChunk) {
+        if (res) res->first_bad_chunk = hq[5];
+        return CKPT_ECORRUPT;
+    }
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_restore(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                            void* stream, ckpt_result* res) {
+    fill_result(res);
+    if (!c || !img || !table) return CKPT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    return restore_impl(c, img, table, o, stream, res);
+}
+
+// ------------------------------------------------------------ host ops
+extern "C" int ckpt_image_bytes(const ckpt_image* img, const void** p, uint64_t* n) {
+    if (!img || !p || !n) return CKPT_EINVAL;
+    *p = img->p;
+    *n = img->n;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_image_import(const void* p, uint64_t n, ckpt_image** out) {
+    if (!out) return CKPT_EINVAL;
+    *out = nullptr;
+    if (!p && n) return CKPT_EINVAL;
+    ImageView v;
+    int rc = parse_image(static_cast<const uint8_t*>(p), n, &v, true);
+    if (rc) return rc;
+    ckpt_image* im = image_new(n);
+    if (!im) return CKPT_ENOMEM;
+    memcpy(im->p, p, n);
+    im->n = n;
+    *out = im;
+    return CKPT_OK;
+}
+
+extern "C" void ckpt_image_free(ckpt_image* img) {
+    if (!img) return;
+    pool().put(img->p, img->cap);
+    delete img;
+}
+
+extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_image** out) {
+    if (!out) return CKPT_EINVAL;
+    *out = nullptr;
+    if (!base || !delta) return CKPT_EINVAL;
+    ImageView b, d;
+    int rc = parse_image(base->p, base->n, &b, true);
+    if (rc) return rc;
+    rc = parse_image(delta->p, delta->n, &d, true);
+    if (rc) return rc;
+    if ((b.flags & 1u) || !(d.flags & 1u) || b.C != d.C) return CKPT_EINVAL;
+    if (d.base_state != b.state_digest) return CKPT_EBASE;
+    const uint32_t C = d.C;
+    // payload offset of each DATA chunk of the base, and base allocations by id
+    std::vector<uint64_t> bpos(b.n_chunks);
+    std::unordered_map<uint64_t, uint64_t> bidx;
+    bidx.reserve(b.n_allocs * 2 + 1);
+    uint64_t pos = 0;
+    for (uint64_t a = 0; a < b.n_allocs; ++a) {
+        const uint64_t size = get64(b.recs + 32 * a + 8), first = get64(b.recs + 32 * a + 16);
+        bidx.emplace(get64(b.recs + 32 * a), a);
+        const uint64_t nk = ceil_div(size, C);
+        for (uint64_t k = 0; k < nk; ++k) {
+            bpos[first + k] = pos;
+            if (b.kinds[first + k] == kData) pos += round16(k + 1 == nk ? size - k * C : C);
+        }
+    }
+    // merged kinds and payload size
+    std::vector<uint8_t> kinds(d.n_chunks);
+    std::vector<const uint8_t*> src(d.n_chunks, nullptr);
+    uint64_t D = 0, dpos = 0;
+    for (uint64_t a = 0; a < d.n_allocs; ++a) {
+        const uint64_t id = get64(d.recs + 32 * a), size = get64(d.recs + 32 * a + 8),
+                       first = get64(d.recs + 32 * a + 16);
+        const uint64_t nk = ceil_div(size, C);
+        auto bi = bidx.find(id);
+        for (uint64_t k = 0; k < nk; ++k) {
+            const uint64_t gi = first + k, l16 = round16(k + 1 == nk ? size - k * C : C);
+            uint8_t kd = d.kinds[gi];
+            if (kd == kData) {
+                src[gi] = d.payload + dpos;
+                dpos += l16;
+            } else if (kd == kUnchanged) {
+                if (bi == bidx.end() || get64(b.recs + 32 * bi->second + 8) != size) return CKPT_EBASE;
+                const uint64_t gb = get64(b.recs + 32 * bi->second + 16) + k;
+                kd = b.kinds[gb];
+                if (kd == kData) src[gi] = b.payload + bpos[gb];
+            }
+            kinds[gi] = kd;
+            if (kd == kData) D += l16;
+        }
+    }
+    ckpt_image* im = image_new(kHeader + d.tl + D);
+    if (!im) return CKPT_ENOMEM;
+    uint8_t* o = im->p;
+    memset(o, 0, kHeader + d.tl);
+    const uint64_t len_a = 32ull * d.n_allocs + 4 * d.n_chunks;
+    memcpy(o + kHeader, d.recs, len_a);
+    memcpy(o + kHeader + len_a, kinds.data(), d.n_chunks);
+    uint64_t op = kHeader + d.tl;
+    for (uint64_t a = 0; a < d.n_allocs; ++a) {
+        const uint64_t size = get64(d.recs + 32 * a + 8), first = get64(d.recs + 32 * a + 16);
+        const uint64_t nk = ceil_div(size, C);
+        for (uint64_t k = 0; k < nk; ++k) {
+            if (!src[first + k]) continue;
+            const uint64_t l16 = round16(k + 1 == nk ? size - k * C : C);
+            memcpy(o + op, src[first + k], l16);
+            op += l16;
+        }
+    }
+    memcpy(o, "MICKPT01", 8);
+    put32(o + 8, 1);
+    put32(o + 12, 0);
+    put32(o + 16, C);
+    put32(o + 20, d.n_allocs);
+    put64(o + 24, d.n_chunks);
+    put64(o + 32, D);
+    put32(o + 40, 0);
+    put32(o + 44, 0);
+    put64(o + 48, d.N);
+    put32(o + 56, host_crc32c(o + kHeader, d.tl));
+    put32(o + 60, host_crc32c(o, 60));
+    im->n = op;
+    *out = im;
+    return CKPT_OK;
+}
+
+extern "C" const char* ckpt_strerror(int code) {
+    switch (code) {
+        case CKPT_OK: return "ok";
+        case CKPT_EINVAL: return "invalid argument";
+        case CKPT_ENOMEM: return "out of memory or staging budget";
+        case CKPT_EHIP: return "HIP runtime error";
+        case CKPT_ECORRUPT: return "image corrupt or verification failed";
+        case CKPT_EMISMATCH: return "allocation table does not match the image";
+        case CKPT_EBASE: return "delta image without its base";
+        case CKPT_ETIMEOUT: return "deadline passed";
+        default: return "unknown error";
+    }
+}
+
+extern "C" uint32_t ckpt_crc32c(const void* p, uint64_t n) { return host_crc32c(p, n); }

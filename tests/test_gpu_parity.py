@@ -1,0 +1,217 @@
+"""GPU parity: images from the HIP path are byte-identical to the CPU
+oracle's, and restores write back exactly the dumped bytes. Tolerance is
+0 bytes (integer / byte work). Every call goes through the C ABI."""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as corc  # noqa: E402
+from paper_2502_16631_amd import mickpt as mk  # noqa: E402
+import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mk.ckpt_ctx_create(0, 1 << 30)
+    yield c
+    mk.ckpt_ctx_destroy(c)
+
+
+def host(table):
+    return workloads.host_copy(table)
+
+
+def gpu_dump(ctx, table, prev=None, **kw):
+    rc, img, res = mk.ckpt_dump(ctx, table, prev=prev, opts=mk.make_opts(**kw))
+    assert rc == 0, mk.ckpt_strerror(rc)
+    return img, res
+
+
+def check_parity(ctx, table, c, prev_gpu=None, prev_oracle=None, **kw):
+    img, res = gpu_dump(ctx, table, prev=prev_gpu, chunk_size=c, **kw)
+    rc, oimg = corc.dump(host(table), c, prev=prev_oracle)
+    assert rc == 0
+    got = img.view()
+    assert got.size == oimg.size, (got.size, oimg.size)
+    if not np.array_equal(got, oimg):
+        diff = np.nonzero(got != oimg)[0]
+        raise AssertionError("image differs at %d bytes, first at %d" % (diff.size, diff[0]))
+    return img, oimg, res
+
+
+def restore_and_compare(ctx, img, table, **kw):
+    targets = [(i, torch.full_like(t, 0x5A) if t.numel() else t.clone()) for i, t in table]
+    rc, res = mk.ckpt_restore(ctx, img, targets, opts=mk.make_opts(**kw))
+    assert rc == 0, (mk.ckpt_strerror(rc), res.first_bad_chunk)
+    torch.cuda.synchronize()
+    for (_, a), (_, b) in zip(table, targets):
+        assert torch.equal(a, b)
+    return res
+
+
+def test_tiny_image_full_dump_restore(ctx):
+    """8 allocations log-uniform in [4 KiB, 4 MiB], 16 MiB, random bytes, 64 KiB chunks."""
+    table = workloads.tiny_image(DEV, seed=1)
+    img, oimg, res = check_parity(ctx, table, 65536)
+    assert res.n_unchanged == 0 and res.n_payload == corc.parse(oimg)[1]["D"]
+    restore_and_compare(ctx, img, table)
+
+
+def _rand_table(rng, gen, n, c, zero_p=0.3, max_chunks=5):
+    sizes, table = [], []
+    for a in range(n):
+        size = int(rng.integers(0, max_chunks * c + 1))
+        if rng.random() < 0.2:
+            size = int(rng.choice([0, 1, 15, 16, 17, c - 1, c, c + 1, 2 * c, 2 * c + 5]))
+        size = max(size, 0)
+        t = torch.randint(0, 256, (size,), dtype=torch.uint8, device=DEV, generator=gen)
+        for lo in range(0, size, c):
+            if rng.random() < zero_p:
+                t[lo:lo + c] = 0
+        table.append((int(rng.integers(1, 1 << 62)), t))
+    return table
+
+
+@pytest.mark.parametrize("c", [1024, 2048, 4096, 16384, 32768, 65536, 131072, 262144])
+def test_chunk_sizes_ragged_tables(ctx, c):
+    rng = np.random.default_rng(c)
+    gen = torch.Generator(device=DEV).manual_seed(c)
+    table = _rand_table(rng, gen, 12, c)
+    img, _, _ = check_parity(ctx, table, c)
+    restore_and_compare(ctx, img, table)
+
+
+@pytest.mark.parametrize("c", [16, 32, 64, 128, 256, 512])
+def test_bruteforce_tiny_chunk_sizes(ctx, c):
+    """Sizes around the chunk edges, contents zero / random / single byte,
+    previous image none / same / one byte changed / resized / renamed."""
+    rng = random.Random(c)
+    gen = torch.Generator(device=DEV).manual_seed(c)
+    sizes = sorted({0, 1, 15, 16, 17, c - 1, c, c + 1, 2 * c, 2 * c + 5})
+    for trial in range(40):
+        n = rng.randint(1, 3)
+        table = []
+        for a in range(n):
+            size = rng.choice(sizes)
+            kind = rng.choice(["zero", "random", "first", "last"])
+            t = torch.zeros(size, dtype=torch.uint8, device=DEV)
+            if kind == "random" and size:
+                t = torch.randint(0, 256, (size,), dtype=torch.uint8, device=DEV, generator=gen)
+            elif kind in ("first", "last") and size:
+                t[0 if kind == "first" else size - 1] = rng.randint(1, 255)
+            table.append((10 + a, t))
+        pk = rng.choice([None, "same", "byte", "resized", "renamed"])
+        prev_g = prev_o = None
+        if pk is not None:
+            pt = []
+            for aid, t in table:
+                x = t.clone()
+                if pk == "byte" and x.numel():
+                    x[rng.randrange(x.numel())] ^= 1
+                if pk == "resized":
+                    x = torch.cat([x, torch.tensor([7], dtype=torch.uint8, device=DEV)])
+                pt.append((aid + (1000 if pk == "renamed" else 0), x))
+            prev_g, _ = gpu_dump(ctx, pt, chunk_size=c)
+            prev_o = prev_g.tobytes()
+        img, _, _ = check_parity(ctx, table, c, prev_gpu=prev_g, prev_oracle=prev_o)
+        if pk is None:
+            restore_and_compare(ctx, img, table)
+
+
+def test_windows_slots_streams_and_shapes_do_not_change_the_image(ctx):
+    rng = np.random.default_rng(21)
+    gen = torch.Generator(device=DEV).manual_seed(21)
+    c = 65536
+    table = _rand_table(rng, gen, 20, c, max_chunks=40)
+    ref, oimg, _ = check_parity(ctx, table, c)
+    variants = [dict(window_bytes=4 * c), dict(window_bytes=c, slots=2), dict(copy_streams=1),
+                dict(copy_streams=4, window_bytes=8 * c), dict(flags=mk.OPT_PER_ALLOC),
+                dict(wg_threads=1024), dict(wg_threads=256), dict(wg_threads=64)]
+    for kw in variants:
+        img, _, _ = check_parity(ctx, table, c, **kw)
+        restore_and_compare(ctx, img, table, **kw)
+
+
+def test_delta_dump_merge_and_in_place_restore(ctx):
+    c = 65536
+    rng = np.random.default_rng(22)
+    gen = torch.Generator(device=DEV).manual_seed(22)
+    base = _rand_table(rng, gen, 10, c, max_chunks=30)
+    new = [(i, t.clone()) for i, t in base]
+    workloads.mutate_runs(new, seed=23, chunk=c, frac=0.2, run_mean=3)
+    new[1] = (new[1][0], torch.zeros_like(new[1][1]))
+    new[2] = (new[2][0] + 77, new[2][1])               # renamed: no match in the base
+    b_img, b_or, _ = check_parity(ctx, base, c)
+    d_img, d_or, res = check_parity(ctx, new, c, prev_gpu=b_img, prev_oracle=b_or)
+    assert res.n_unchanged > 0
+    # same delta when the previous image is not resident (imported copy)
+    rc, b_imp = mk.ckpt_image_import(b_img.view())
+    assert rc == 0
+    check_parity(ctx, new, c, prev_gpu=b_imp, prev_oracle=b_or)
+    # merge == full dump (library and oracle)
+    rc, merged = mk.ckpt_merge(b_img, d_img)
+    assert rc == 0
+    rc, full_or = corc.dump(host(new), c)
+    assert np.array_equal(merged.view(), full_or)
+    # in-place: restore base, then the delta
+    targets = [(i, torch.zeros_like(t)) for i, t in new]
+    base_targets = [(i, t) for (i, _), (_, t) in zip(base, targets)]
+    assert mk.ckpt_restore(ctx, b_img, base_targets)[0] == 0
+    rc, r = mk.ckpt_restore(ctx, d_img, targets)
+    assert rc == 0, mk.ckpt_strerror(rc)
+    torch.cuda.synchronize()
+    for (_, a), (_, b) in zip(new, targets):
+        assert torch.equal(a, b)
+
+
+def test_error_paths_match_the_oracle(ctx):
+    c = 4096
+    rng = np.random.default_rng(24)
+    gen = torch.Generator(device=DEV).manual_seed(24)
+    table = _rand_table(rng, gen, 6, c, zero_p=0.2)
+    img, oimg, _ = check_parity(ctx, table, c)
+    raw = img.tobytes()
+    n = len(table)
+    nc = corc.parse(oimg)[1]["n_chunks"]
+    tl = (32 * n + 5 * nc + 15) & ~15
+    spots = [0, 12, 30, 61, 64 + 3, 64 + 32 * n + 2, 64 + 32 * n + 4 * nc]
+    if len(raw) > 64 + tl:
+        spots += [64 + tl + 1, len(raw) - 1]
+    for pos in spots:
+        bad = bytearray(raw)
+        bad[pos] ^= 0x10
+        bad = bytes(bad)
+        hosts = [(i, np.zeros(t.numel(), np.uint8)) for i, t in table]
+        want = corc.restore(bad, hosts)
+        rc, bimg = mk.ckpt_image_import(bad)
+        if rc != 0:
+            # the import validates header and tables on the host
+            assert rc == want[0] == mk.CKPT_ECORRUPT
+            continue
+        targets = [(i, torch.zeros_like(t)) for i, t in table]
+        rc, res = mk.ckpt_restore(ctx, bimg, targets)
+        assert (rc, res.first_bad_chunk) == want, pos
+    # table mismatch and wrong base
+    t2 = [(i + 1, t) for i, t in table]
+    assert mk.ckpt_restore(ctx, img, t2)[0] == mk.CKPT_EMISMATCH
+    new = [(i, t.clone()) for i, t in table]
+    workloads.mutate_runs(new, seed=25, chunk=c, frac=0.3, run_mean=2)
+    d_img, d_or, _ = check_parity(ctx, new, c, prev_gpu=img, prev_oracle=oimg)
+    wrong = [(i, torch.full_like(t, 3)) for i, t in table]
+    rc, res = mk.ckpt_restore(ctx, d_img, wrong)
+    want = corc.restore(d_or, [(i, np.full(t.numel(), 3, np.uint8)) for i, t in table])
+    assert (rc, res.first_bad_chunk) == want and rc == mk.CKPT_EBASE
