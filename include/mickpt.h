@@ -140,6 +140,18 @@ int  ckpt_dump(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* p
 int  ckpt_restore(ckpt_ctx* ctx, const ckpt_image* img, const ckpt_alloc_table* table,
                   const ckpt_opts* opts, void* stream, ckpt_result* res);
 
+/* ------------------------------------------------------------------ autotuner */
+/* Batched form: choose chunk size (16, 64 or 256 KiB), work-group width and
+ * copy-stream count for `table` by timing trial dumps of a bounded sample of
+ * it (allocations spread over the table, about sample_bytes in total; 0 =
+ * 2 GB). flags are the CKPT_OPT_* flags the caller will dump with. Fills
+ * *best (to pass to ckpt_dump) and, if non-NULL, *gbps with the best trial's
+ * logical GB/s. Results are cached in the context per table shape (count and
+ * size class of the allocations), so later calls return at once. The
+ * allocations are only read. */
+int  ckpt_autotune(ckpt_ctx* ctx, const ckpt_alloc_table* table, uint64_t sample_bytes, uint32_t flags,
+                   ckpt_opts* best, double* gbps);
+
 /* ------------------------------------------------------------------ host ops */
 /* Fold a delta into the full image of its base (host memory only): the
  * result equals a full dump of the delta's state. CKPT_EINVAL if base is a

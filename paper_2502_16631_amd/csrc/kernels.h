@@ -23,11 +23,24 @@ struct ChunkJob {
     const uint64_t* off;         // restore: payload offset of chunk g
     uint64_t slot_base;          // restore: payload offset of the window start
     uint64_t* status;            // dump: look-back status, indexed by g - g0
-    uint32_t* ticket;            // zero before launch
     uint64_t* wtotal;            // dump: payload bytes of the window
     unsigned long long* bad;     // verify / restore: lowest failing chunk (init ~0)
     uint32_t* err;               // internal error flag (look-back time-out)
     uint32_t epoch;              // look-back epoch of this launch (1 .. 2^22-1)
+    uint32_t pad;
+};
+
+// Several jobs in one persistent launch (continuous batching): the jobs'
+// chunk ranges are laid end to end in one ticket space; every job keeps its
+// own descriptors, tables, staging window and look-back scope, so a job's
+// result does not depend on what it shares the launch with. All jobs of a
+// launch use the same chunk size and tile shape (one set of LDS tables).
+constexpr int kMaxJobs = 16;
+struct JobList {
+    ChunkJob job[kMaxJobs];
+    uint64_t prefix[kMaxJobs + 1];   // ticket range of job j: [prefix[j], prefix[j+1])
+    uint32_t* ticket;                // shared ticket counter, zero before launch
+    uint32_t n_jobs;
     uint32_t pad;
 };
 
@@ -66,7 +79,7 @@ struct CombineJob {
 };
 
 bool tile_supported(int T, int K);
-hipError_t launch_chunks(int T, int K, int mode, const ChunkJob& job, int grid, hipStream_t s);
+hipError_t launch_chunks(int T, int K, int mode, const JobList& jl, int grid, hipStream_t s);
 hipError_t chunks_occupancy(int T, int K, int mode, int* blocks_per_cu);
 hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s);
 hipError_t launch_combine(const CombineJob& job, hipStream_t s);

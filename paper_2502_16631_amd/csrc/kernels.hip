@@ -266,7 +266,7 @@ __device__ inline uint32_t wg_xor(uint32_t x, uint32_t* s_red) {
 // shapes hold 32 VGPRs of chunk data between load and store.
 template <int T, int K, int MODE>
 __global__ void __launch_bounds__(T < 64 ? 64 : T) __attribute__((amdgpu_waves_per_eu(4)))
-k_chunks(ChunkJob job) {
+k_chunks(JobList jl) {
     constexpr int NT = T < 64 ? 64 : T;
     constexpr int NW = NT / 64;
     constexpr uint32_t TILE = 16u * T * K;
@@ -278,20 +278,26 @@ k_chunks(ChunkJob job) {
 
     const int tid = threadIdx.x;
     const bool active = T >= 64 || tid < T;
-    for (int i = tid; i < 16 * 256; i += NT) s_dt[i] = job.ec->dt[i];
-    for (int i = tid; i < 4 * 256; i += NT) s_jt[i] = job.ec->jt[i];
-    const uint32_t lanec = active ? job.ec->lane[tid] : 0u;
-    const uint32_t full_init = job.ec->full_init;
-    const uint32_t C = job.C;
+    const EngineConsts* ec = jl.job[0].ec;
+    for (int i = tid; i < 16 * 256; i += NT) s_dt[i] = ec->dt[i];
+    for (int i = tid; i < 4 * 256; i += NT) s_jt[i] = ec->jt[i];
+    const uint32_t lanec = active ? ec->lane[tid] : 0u;
+    const uint32_t full_init = ec->full_init;
+    const uint32_t C = jl.job[0].C;
+    const uint64_t total = jl.prefix[jl.n_jobs];
     const uint32_t log2c = 31 - __builtin_clz(C);
     const uint32_t P = C / TILE;        // passes per chunk (C is a multiple of TILE)
     __syncthreads();
 
     for (uint32_t it = 0;; ++it) {
-        if (tid == 0) s_tk[it & 1] = atomicAdd(job.ticket, 1u);
+        if (tid == 0) s_tk[it & 1] = atomicAdd(jl.ticket, 1u);
         __syncthreads();
-        const uint64_t g = job.g0 + (uint64_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
-        if (g >= job.g1) break;
+        const uint64_t tk = (uint64_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
+        if (tk >= total) break;
+        uint32_t jj = 0;
+        while (jj + 1 < jl.n_jobs && jl.prefix[jj + 1] <= tk) ++jj;
+        const ChunkJob& job = jl.job[jj];
+        const uint64_t g = job.g0 + (tk - jl.prefix[jj]);
         // Opaque per-chunk copies of per-lane values: without them the
         // compiler hoists 32 multiples of the lane constant and one address
         // per row out of the loop, which costs ~50 VGPRs per lane.
@@ -540,13 +546,13 @@ __global__ void k_fill32(uint32_t* p, uint32_t v, uint64_t n) {
 }
 
 template <int T, int K>
-hipError_t launch_tk(int mode, const ChunkJob& job, int grid, hipStream_t s) {
+hipError_t launch_tk(int mode, const JobList& jl, int grid, hipStream_t s) {
     constexpr int NT = T < 64 ? 64 : T;
     switch (mode) {
-        case kModeDump: hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, job); break;
-        case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, job); break;
-        case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, job); break;
-        case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, job); break;
+        case kModeDump: hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, jl); break;
+        case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, jl); break;
+        case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, jl); break;
+        case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, jl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -578,8 +584,9 @@ bool tile_supported(int T, int K) {
     return false;
 }
 
-hipError_t launch_chunks(int T, int K, int mode, const ChunkJob& job, int grid, hipStream_t s) {
-#define MK_LAUNCH(t, k) if (T == t && K == k) return launch_tk<t, k>(mode, job, grid, s);
+hipError_t launch_chunks(int T, int K, int mode, const JobList& jl, int grid, hipStream_t s) {
+    if (jl.n_jobs < 1 || jl.n_jobs > (uint32_t)kMaxJobs) return hipErrorInvalidValue;
+#define MK_LAUNCH(t, k) if (T == t && K == k) return launch_tk<t, k>(mode, jl, grid, s);
     MK_TILES(MK_LAUNCH)
 #undef MK_LAUNCH
     return hipErrorInvalidValue;

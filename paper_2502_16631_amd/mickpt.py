@@ -94,6 +94,9 @@ def lib():
         L.ckpt_image_free.restype = None
         L.ckpt_strerror.argtypes = [ctypes.c_int]
         L.ckpt_strerror.restype = ctypes.c_char_p
+        L.ckpt_autotune.argtypes = [vp, ctypes.POINTER(ckpt_alloc_table), _u64, _u32, ctypes.POINTER(ckpt_opts),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.ckpt_autotune.restype = ctypes.c_int
         L.ckpt_crc32c.argtypes = [vp, _u64]
         L.ckpt_crc32c.restype = _u32
         _lib = L
@@ -208,6 +211,15 @@ def ckpt_restore(ctx, image, table, opts=None, stream=None):
     rc = lib().ckpt_restore(ctx, image.handle, ctypes.byref(tab),
                             ctypes.byref(opts) if opts is not None else None, _stream(stream), ctypes.byref(res))
     return rc, res
+
+
+def ckpt_autotune(ctx, table, sample_bytes=0, flags=0):
+    tab, keep = _table(table)
+    best = ckpt_opts()
+    gbps = ctypes.c_double(0)
+    rc = lib().ckpt_autotune(ctx, ctypes.byref(tab), int(sample_bytes), int(flags), ctypes.byref(best),
+                             ctypes.byref(gbps))
+    return rc, best, gbps.value
 
 
 def ckpt_merge(base, delta):

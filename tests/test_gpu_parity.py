@@ -146,6 +146,34 @@ def test_windows_slots_streams_and_shapes_do_not_change_the_image(ctx):
         restore_and_compare(ctx, img, table, **kw)
 
 
+def test_graph_replays_and_per_allocation_launches(ctx):
+    """Batched form: the captured graph is replayed on new contents of the same
+    table; the per-allocation launch baseline gives the same image."""
+    c = 65536
+    rng = np.random.default_rng(26)
+    gen = torch.Generator(device=DEV).manual_seed(26)
+    table = _rand_table(rng, gen, 40, c, max_chunks=6)
+    prev_g = prev_o = None
+    for rep in range(4):
+        if rep:
+            workloads.mutate_runs(table, seed=27 + rep, chunk=c, frac=0.2, run_mean=2)
+        img, oimg, _ = check_parity(ctx, table, c, prev_gpu=prev_g if rep == 3 else None,
+                                    prev_oracle=prev_o if rep == 3 else None, flags=mk.OPT_GRAPH)
+        prev_g, prev_o = img, oimg
+    check_parity(ctx, table, c, flags=mk.OPT_PER_ALLOC)
+
+
+def test_autotuned_options_give_the_oracle_image(ctx):
+    c_rng = np.random.default_rng(28)
+    gen = torch.Generator(device=DEV).manual_seed(28)
+    table = _rand_table(c_rng, gen, 30, 65536, max_chunks=12)
+    rc, best, gbps = mk.ckpt_autotune(ctx, table, sample_bytes=8 << 20)
+    assert rc == 0 and best.chunk_size in (16384, 65536, 262144) and gbps > 0
+    check_parity(ctx, table, best.chunk_size, wg_threads=best.wg_threads, copy_streams=best.copy_streams)
+    rc2, best2, _ = mk.ckpt_autotune(ctx, table, sample_bytes=8 << 20)     # cached
+    assert rc2 == 0 and best2.chunk_size == best.chunk_size
+
+
 def test_delta_dump_merge_and_in_place_restore(ctx):
     c = 65536
     rng = np.random.default_rng(22)
