@@ -1,0 +1,266 @@
+"""The batched, incremental and served forms of the benchmark (bench.py
+--form ...). Each returns one JSON-ready dict. Inputs come from workloads.py
+(seeded, synthetic, on the device)."""
+import heapq
+import sys
+import time
+
+import numpy as np
+
+import workloads
+
+C = 65536
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))] if xs else None
+
+
+def _nbytes(table):
+    return sum(t.numel() * t.element_size() for _, t in table)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def incremental(args, torch, mk, link):
+    """HPC image (512 fp64/int32 allocations, 40 GB, ~60 % zero chunks): a base
+    dump, then 5 % of chunks rewritten in clustered runs; timed: the delta
+    dump against the base, the restore of the base and the in-place restore
+    of the delta."""
+    total = int(40e9 * args.scale)
+    table, masks = workloads.hpc_state("cuda", seed=3, total=total)
+    torch.cuda.synchronize()
+    N = _nbytes(table)
+    ctx = mk.ckpt_ctx_create(0, max(args.budget, N + (1 << 30)))
+    opts = mk.make_opts(chunk_size=C)
+    rc, base, bres = mk.ckpt_dump(ctx, table, opts=opts)
+    assert rc == 0
+    dirty = workloads.mutate_runs(table, seed=33, chunk=C, frac=0.05, run_mean=16)
+    torch.cuda.synchronize()
+    t_delta, t_base, t_apply, kern = [], [], [], []
+    D = 0
+    for k in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        rc, delta, dres = mk.ckpt_dump(ctx, table, prev=base, opts=opts)
+        t1 = time.perf_counter()
+        assert rc == 0
+        rc, r1 = mk.ckpt_restore(ctx, base, table, opts=opts)           # back to the base state
+        t2 = time.perf_counter()
+        assert rc == 0, mk.ckpt_strerror(rc)
+        rc, r2 = mk.ckpt_restore(ctx, delta, table, opts=opts)          # base + delta, in place
+        t3 = time.perf_counter()
+        assert rc == 0, mk.ckpt_strerror(rc)
+        if k >= args.warmup:
+            t_delta.append(t1 - t0)
+            t_base.append(t2 - t1)
+            t_apply.append(t3 - t2)
+            kern.append(dres.ns_kernel)
+            D = dres.n_payload
+            info = dres.as_dict()
+        delta.free()
+        _log("step %d: delta dump %.3f s, base restore %.3f s, delta apply %.3f s" % (k, t1 - t0, t2 - t1, t3 - t2))
+    mk.ckpt_ctx_destroy(ctx)
+    nc = info["n_chunks"]
+    k_avg = sum(kern) / len(kern) / 1e9
+    alg = N + D + 9 * nc
+    td = sum(t_delta) / len(t_delta)
+    return {
+        "metric": "incremental dump / base+delta restore GB/s at 1 GPU", "form": "incremental",
+        "value": round(N / td / 1e9, 3), "unit": "GB/s (logical N per delta-dump second)",
+        "config": {"workload": "HPC image: %d fp64/int32 allocations, %.1f GB, %.1f%% zero chunks, %d of %d chunks "
+                               "rewritten in runs (mean 16)" % (len(table), N / 1e9, 100.0 * info["n_zero"] / nc, dirty, nc),
+                   "chunk": C, "N_bytes": N, "base_D_bytes": bres.n_payload, "delta_D_bytes": D,
+                   "unchanged_chunks": info["n_unchanged"]},
+        "delta_dump_ms_p50": round(_pct(t_delta, 50) * 1e3, 2),
+        "base_restore_ms_p50": round(_pct(t_base, 50) * 1e3, 2),
+        "delta_apply_ms_p50": round(_pct(t_apply, 50) * 1e3, 2),
+        "delta_link_GBps": round((D + info["link_bytes"] - D) / td / 1e9, 2),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+        "roofline": {"bound": "hbm", "achieved": round(alg / k_avg / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(alg / k_avg / 1e9 / 8000.0, 4), "kernel": "k_chunks dump mode (delta)"},
+    }
+
+
+def batched(args, torch, mk, link):
+    """10,000 allocations log-uniform in [256 B, 256 MiB] (60 GB, ~30 % zero
+    chunks): autotuned options, the graph-captured single-launch form and the
+    per-allocation launch form, dump + restore each."""
+    total = int(60e9 * args.scale)
+    table = workloads.fragmented_state("cuda", seed=4, total=total)
+    torch.cuda.synchronize()
+    N = _nbytes(table)
+    ctx = mk.ckpt_ctx_create(0, max(args.budget, N + (4 << 30)))
+    t0 = time.perf_counter()
+    rc, best, tuned_gbps = mk.ckpt_autotune(ctx, table, sample_bytes=int(4e9), flags=mk.OPT_GRAPH)
+    t_tune = time.perf_counter() - t0
+    assert rc == 0
+    _log("autotune: chunk %d, threads %d, streams %d (%.1f GB/s on the sample, %.1f s)"
+         % (best.chunk_size, best.wg_threads, best.copy_streams, tuned_gbps, t_tune))
+    forms = {
+        "batched": mk.make_opts(chunk_size=best.chunk_size, wg_threads=best.wg_threads,
+                                copy_streams=best.copy_streams, flags=mk.OPT_GRAPH),
+        "per_alloc": mk.make_opts(chunk_size=best.chunk_size, wg_threads=best.wg_threads,
+                                  copy_streams=best.copy_streams, flags=mk.OPT_PER_ALLOC),
+    }
+    out = {}
+    ref_bytes = None
+    for name, opts in forms.items():
+        td, tr, kern = [], [], []
+        for k in range(args.warmup + args.steps):
+            t0 = time.perf_counter()
+            rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+            t1 = time.perf_counter()
+            assert rc == 0
+            rc, rres = mk.ckpt_restore(ctx, img, table, opts=opts)
+            t2 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            if k >= args.warmup:
+                td.append(t1 - t0)
+                tr.append(t2 - t1)
+                kern.append(res.ns_kernel)
+                info = res.as_dict()
+            if ref_bytes is None:
+                ref_bytes = (img.nbytes(), int(np.frombuffer(img.view()[:64].tobytes(), np.uint32)[15]))
+            else:
+                assert (img.nbytes(), int(np.frombuffer(img.view()[:64].tobytes(), np.uint32)[15])) == ref_bytes
+            img.free()
+            _log("%s step %d: dump %.3f s restore %.3f s" % (name, k, t1 - t0, t2 - t1))
+        out[name] = {"dump_GBps": round(N / (sum(td) / len(td)) / 1e9, 3),
+                     "restore_GBps": round(N / (sum(tr) / len(tr)) / 1e9, 3),
+                     "dump_p50_ms": round(_pct(td, 50) * 1e3, 2), "dump_p99_ms": round(_pct(td, 99) * 1e3, 2),
+                     "launches_per_dump": info["windows"]}
+    mk.ckpt_ctx_destroy(ctx)
+    b, p = out["batched"], out["per_alloc"]
+    return {
+        "metric": "batched dump/restore GB/s at 1 GPU vs per-allocation launches", "form": "batched",
+        "value": round(2 * N / (N / b["dump_GBps"] / 1e9 + N / b["restore_GBps"] / 1e9) / 1e9, 3), "unit": "GB/s",
+        "config": {"workload": "fragmented: %d allocations, %.1f GB, %d chunks (%d zero)"
+                               % (len(table), N / 1e9, info["n_chunks"], info["n_zero"]),
+                   "chunk": best.chunk_size, "wg_threads": best.wg_threads, "copy_streams": best.copy_streams,
+                   "autotune_s": round(t_tune, 2)},
+        "batched": b, "per_alloc": p,
+        "dump_speedup_vs_per_alloc": round(b["dump_GBps"] / p["dump_GBps"], 3),
+        "restore_speedup_vs_per_alloc": round(b["restore_GBps"] / p["restore_GBps"], 3),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+        "images_identical": True,
+    }
+
+
+def serve(args, torch, mk, link):
+    """32 tenants with device states log-uniform in [100 MB, 8 GB] (scaled to
+    ~48 GB in total; kinds cycle DL-like / HPC-like / random), Poisson
+    arrivals at `rate` requests per second for `duration` seconds, uniform
+    tenant, 50 % dumps (half of them incremental after 5 % of the tenant's
+    chunks were rewritten) and 50 % restores of the tenant's last image; a
+    tenant's requests run one at a time. Latency is arrival to completion."""
+    rng = np.random.default_rng(5)
+    n_t = 32
+    sizes = workloads.loguniform_sizes(n_t, 100 * 10**6, 8 * 10**9, int(48e9 * args.scale), 1 << 20, seed=5)
+    tenants = []
+    for t, size in enumerate(sizes):
+        kind = t % 3
+        if kind == 0:       # DL-like: bf16 weights and fp32 optimizer state
+            gen = torch.Generator(device="cuda").manual_seed(100 + t)
+            w = torch.empty(size // 4, dtype=torch.bfloat16, device="cuda").normal_(0, 0.02, generator=gen)
+            m = torch.empty(size // 4, dtype=torch.float32, device="cuda").normal_(0, 1e-3, generator=gen)
+            table = [(0, w), (1, m)]
+        elif kind == 1:     # HPC-like: zero runs
+            table, _ = workloads.hpc_state("cuda", seed=100 + t, total=size, n=8, chunk=C)
+        else:               # random bytes with zero blocks
+            table = workloads.fragmented_state("cuda", seed=100 + t, total=size, n=16)
+        tenants.append({"table": table, "N": _nbytes(table), "last": None, "busy": None, "backlog": []})
+    torch.cuda.synchronize()
+    N_all = sum(t["N"] for t in tenants)
+    ctx = mk.ckpt_ctx_create(0, 64 << 30)
+    opts = mk.make_opts(chunk_size=C)
+    for t in tenants:
+        rc, img, _ = mk.ckpt_dump(ctx, t["table"], opts=opts)
+        assert rc == 0
+        t["last"] = img
+    _log("tenants ready: %.1f GB in %d tenants" % (N_all / 1e9, n_t))
+    srv = mk.ckpt_serve_create(ctx, 16, 64 << 30)
+    # arrivals
+    arrivals, tt = [], 0.0
+    while True:
+        tt += rng.exponential(1.0 / args.rate)
+        if tt > args.duration:
+            break
+        r = rng.random()
+        arrivals.append((tt, int(rng.integers(0, n_t)), "restore" if r < 0.5 else ("delta" if r < 0.75 else "full")))
+    lat, done_bytes, n_done, n_fail = [], 0, 0, 0
+    kinds_done = {"restore": 0, "delta": 0, "full": 0}
+    inflight = {}
+    t_start = time.perf_counter()
+    ai = 0
+    old_images = []
+
+    def submit(tid, kind, t_arr):
+        ten = tenants[tid]
+        if kind == "restore":
+            rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, ten["table"], img=ten["last"], tenant=tid)
+        else:
+            prev = None
+            if kind == "delta":
+                workloads.mutate_runs(ten["table"], seed=int(rng.integers(1 << 30)), chunk=C, frac=0.05, run_mean=16)
+                torch.cuda.synchronize()
+                prev = ten["last"]
+            rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, ten["table"], prev=prev, tenant=tid)
+        assert rc == 0
+        ten["busy"] = tk
+        inflight[tk] = (tid, kind, t_arr)
+
+    while ai < len(arrivals) or inflight:
+        now = time.perf_counter() - t_start
+        while ai < len(arrivals) and arrivals[ai][0] <= now:
+            t_arr, tid, kind = arrivals[ai]
+            ai += 1
+            if tenants[tid]["busy"] is None:
+                submit(tid, kind, t_arr)
+            else:
+                tenants[tid]["backlog"].append((kind, t_arr))
+        for tk in list(inflight):
+            done, rc, img, _ = mk.ckpt_serve_poll(srv, tk)
+            if not done:
+                continue
+            tid, kind, t_arr = inflight.pop(tk)
+            ten = tenants[tid]
+            ten["busy"] = None
+            lat.append(time.perf_counter() - t_start - t_arr)
+            if rc != 0:
+                n_fail += 1
+            else:
+                n_done += 1
+                kinds_done[kind] += 1
+                done_bytes += ten["N"]
+                if img is not None:
+                    old_images.append(ten["last"])
+                    ten["last"] = img
+            if ten["backlog"]:
+                k2, ta2 = ten["backlog"].pop(0)
+                submit(tid, k2, ta2)
+        # images no request refers to any more
+        busy_imgs = {id(tenants[i]["last"]) for i in range(n_t)}
+        old_images = [im for im in old_images if id(im) in busy_imgs]
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t_start
+    st = mk.ckpt_serve_stats(srv)
+    mk.ckpt_serve_destroy(srv)
+    mk.ckpt_ctx_destroy(ctx)
+    return {
+        "metric": "served dump/restore throughput and p50/p99 latency at 1 GPU", "form": "serve",
+        "value": round(done_bytes / wall / 1e9, 3), "unit": "GB/s (logical, completed requests)",
+        "config": {"workload": "%d tenants, %.1f GB of device state, Poisson %.1f req/s for %.0f s"
+                               % (n_t, N_all / 1e9, args.rate, args.duration), "chunk": C,
+                   "staging_budget": 64 << 30, "max_active": 16},
+        "requests": len(arrivals), "completed": n_done, "failed": n_fail, "by_kind": kinds_done,
+        "latency_p50_ms": round(_pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(_pct(lat, 99) * 1e3, 2),
+        "server_p50_ms": round(st.p50_ns / 1e6, 2), "server_p99_ms": round(st.p99_ns / 1e6, 2),
+        "server_mean_wait_ms": round(st.mean_wait_ns / 1e6, 2),
+        "merged_launches": st.launches, "max_batch": st.max_batch,
+        "link_GBps": round(st.bytes_link / wall / 1e9, 3),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+        "wall_s": round(wall, 2),
+    }

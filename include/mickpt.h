@@ -170,6 +170,55 @@ const char* ckpt_strerror(int code);
 /* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes. */
 uint32_t ckpt_crc32c(const void* p, uint64_t n);
 
+/* ------------------------------------------------------------------ serving */
+/* A request loop over one context (served form). Dump and restore requests
+ * from many tenants are admitted in arrival order as lanes and staging
+ * memory free up (each admitted request holds two staging windows of the
+ * budget); the next ready window of every admitted request joins one shared
+ * persistent launch per tick (continuous batching), dumps and restores on
+ * separate streams so their work overlaps on the device. Each request's
+ * result is the same as that of the plain calls (its image is byte-identical
+ * to ckpt_dump's with 64 KiB chunks). Tenants' digest tables stay resident
+ * in the context for their incremental dumps. */
+typedef struct ckpt_server ckpt_server;
+#define CKPT_REQ_DUMP     1
+#define CKPT_REQ_RESTORE  2
+typedef struct {
+    uint32_t kind;                   /* CKPT_REQ_DUMP or CKPT_REQ_RESTORE                          */
+    uint32_t tenant;                 /* caller's tenant number (informational)                   */
+    const ckpt_alloc_table* table;   /* entries copied at submit; buffers borrowed until done    */
+    const ckpt_image* prev;          /* dump: previous image (delta), or NULL; borrowed           */
+    const ckpt_image* img;           /* restore: image to apply; borrowed until done             */
+    uint64_t deadline_ns;            /* 0 = none; else CLOCK_MONOTONIC time after which a request
+                                        still waiting for admission fails with CKPT_ETIMEOUT     */
+} ckpt_request;
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t bytes_logical;          /* sum of N over completed requests                          */
+    uint64_t bytes_link;             /* sum of image bytes moved over the host link              */
+    uint64_t launches;               /* merged kernel launches                                    */
+    uint64_t max_batch;              /* most requests sharing one launch                          */
+    uint64_t p50_ns, p99_ns;         /* latency percentiles, submit to completion                 */
+    uint64_t mean_wait_ns;           /* mean wait for admission                                   */
+} ckpt_server_stats;
+/* Create a server that drives ctx from its own thread (other calls on ctx
+ * are serialized with it) with at most max_active requests in flight
+ * (1..16; 0 = 16) and `budget` bytes of staging for admission (0 = the
+ * context's budget; at least two 256 MiB windows). */
+int  ckpt_serve_create(ckpt_ctx* ctx, uint32_t max_active, uint64_t budget, ckpt_server** out);
+/* Queue a request; *ticket >= 1 identifies it. Does not wait for the GPU. */
+int  ckpt_serve_submit(ckpt_server* s, const ckpt_request* rq, uint64_t* ticket);
+/* 1 if the request is done (*rc = its result code; *out = the new image of a
+ * dump, owned by the caller, or freed if out is NULL; *latency_ns = submit
+ * to completion), 0 if pending, CKPT_EINVAL for an unknown ticket. A done
+ * ticket is forgotten after it has been polled. */
+int  ckpt_serve_poll(ckpt_server* s, uint64_t ticket, int* rc, ckpt_image** out, uint64_t* latency_ns);
+/* Wait until every submitted request has completed. */
+int  ckpt_serve_drain(ckpt_server* s);
+int  ckpt_serve_stats(ckpt_server* s, ckpt_server_stats* st);
+/* Finish the queued work, stop the thread, free lanes and unpolled results. */
+void ckpt_serve_destroy(ckpt_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,9 +12,12 @@ hipcc "${FLAGS[@]}" -c "$SRC/kernels.hip" -o "$BUILD/kernels.o" &
 p1=$!
 hipcc "${FLAGS[@]}" -c "$SRC/runtime.hip" -o "$BUILD/runtime.o" &
 p2=$!
+hipcc "${FLAGS[@]}" -c "$SRC/serve.hip" -o "$BUILD/serve.o" &
+p4=$!
 hipcc -O2 -std=c++17 -fPIC -Wall -c "$SRC/hostmath.cpp" -o "$BUILD/hostmath.o" &
 p3=$!
-wait $p1; wait $p2; wait $p3
-hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/hostmath.o" -lpthread
+wait $p1; wait $p2; wait $p3; wait $p4
+hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/serve.o" \
+    "$BUILD/hostmath.o" -lpthread
 mv "$OUT.tmp" "$OUT"
 echo "built $OUT"

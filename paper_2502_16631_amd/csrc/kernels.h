@@ -12,6 +12,7 @@ struct ChunkJob {
     const AllocDesc* allocs;
     uint32_t n_allocs;
     uint32_t C;                  // chunk size
+    const uint32_t* amap;        // allocation of chunk g at [g], or nullptr (binary search)
     uint64_t g0, g1;
     const EngineConsts* ec;      // tables for (T, C)
     uint32_t* crc_out;           // dump / digest: digest of chunk g at [g]
@@ -49,6 +50,7 @@ struct OffJob {
     const AllocDesc* allocs;
     uint32_t n_allocs;
     uint32_t C;
+    const uint32_t* amap;        // allocation of chunk g, or nullptr
     uint64_t n_chunks;
     const uint8_t* kind;
     uint64_t* off;               // [n_chunks]
@@ -83,6 +85,8 @@ hipError_t launch_chunks(int T, int K, int mode, const JobList& jl, int grid, hi
 hipError_t chunks_occupancy(int T, int K, int mode, int* blocks_per_cu);
 hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s);
 hipError_t launch_combine(const CombineJob& job, hipStream_t s);
+hipError_t launch_chunk_map(const AllocDesc* allocs, uint32_t n_allocs, uint32_t C, uint32_t* map, hipStream_t s);
+hipError_t launch_store_descs(AllocDesc* dst, const AllocDesc& a, const AllocDesc& b, hipStream_t s);
 hipError_t launch_fill64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 

@@ -289,11 +289,16 @@ k_chunks(JobList jl) {
     const uint32_t P = C / TILE;        // passes per chunk (C is a multiple of TILE)
     __syncthreads();
 
+    // The next ticket is fetched while the current chunk is processed, so
+    // the atomic's latency is hidden. A work-group holds at most two
+    // tickets, its current one and the next; the chunks before its current
+    // one are held by running work-groups, so every look-back wait ends.
+    if (tid == 0) s_tk[0] = atomicAdd(jl.ticket, 1u);
     for (uint32_t it = 0;; ++it) {
-        if (tid == 0) s_tk[it & 1] = atomicAdd(jl.ticket, 1u);
         __syncthreads();
         const uint64_t tk = (uint64_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
         if (tk >= total) break;
+        if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(jl.ticket, 1u);
         uint32_t jj = 0;
         while (jj + 1 < jl.n_jobs && jl.prefix[jj + 1] <= tk) ++jj;
         const ChunkJob& job = jl.job[jj];
@@ -311,7 +316,7 @@ k_chunks(JobList jl) {
             if (MODE == kModeVerify && kd_in != kUnchanged) continue;
             if (MODE == kModeRestore && kd_in == kUnchanged) continue;
         }
-        const uint32_t a = find_alloc(job.allocs, job.n_allocs, g);
+        const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);
         const AllocDesc ad = job.allocs[a];
         const uint64_t k = g - ad.first;
         const uint64_t nk = (ad.size + C - 1) >> log2c;
@@ -441,7 +446,7 @@ __global__ void __launch_bounds__(256) k_offsets(OffJob job) {
         uint32_t cz = 0, cd = 0, cu = 0, ci = 0;
         if (g < job.n_chunks) {
             const uint8_t kd = job.kind[g];
-            const uint32_t a = find_alloc(job.allocs, job.n_allocs, g);
+            const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);
             const uint64_t first = job.allocs[a].first, size = job.allocs[a].size;
             const uint64_t nk = (size + job.C - 1) / job.C;
             const uint64_t len = (g - first + 1 == nk) ? job.allocs[a].tail_len : job.C;
@@ -536,6 +541,23 @@ __global__ void __launch_bounds__(256) k_combine(CombineJob job) {
     }
 }
 
+// Chunk -> allocation map: work-group a writes a over its chunk range.
+__global__ void __launch_bounds__(256) k_chunk_map(const AllocDesc* allocs, uint32_t n, uint32_t C, uint32_t* map) {
+    for (uint32_t a = blockIdx.x; a < n; a += gridDim.x) {
+        const uint64_t first = allocs[a].first, nk = (allocs[a].size + C - 1) / C;
+        for (uint64_t k = threadIdx.x; k < nk; k += blockDim.x) map[first + k] = a;
+    }
+}
+
+// Two descriptors passed by value (kernel arguments are captured at launch,
+// so the host copy may go away at once, also inside a captured graph).
+__global__ void k_store_descs(AllocDesc* dst, AllocDesc a, AllocDesc b) {
+    if (threadIdx.x == 0) {
+        dst[0] = a;
+        dst[1] = b;
+    }
+}
+
 __global__ void k_fill64(uint64_t* p, uint64_t v, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -607,6 +629,17 @@ hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s) {
 hipError_t launch_combine(const CombineJob& job, hipStream_t s) {
     if (job.n_allocs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_combine, dim3(job.n_allocs), dim3(256), 0, s, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_map(const AllocDesc* allocs, uint32_t n_allocs, uint32_t C, uint32_t* map, hipStream_t s) {
+    if (n_allocs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_map, dim3(n_allocs < 4096 ? n_allocs : 4096), dim3(256), 0, s, allocs, n_allocs, C, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_descs(AllocDesc* dst, const AllocDesc& a, const AllocDesc& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_descs, dim3(1), dim3(64), 0, s, dst, a, b);
     return hipGetLastError();
 }
 

@@ -38,11 +38,8 @@
 
 using namespace mk;
 
-namespace {
+namespace mk {
 
-constexpr uint64_t kNoChunk = ~0ull;
-constexpr uint64_t kHeader = 64;
-constexpr uint32_t kDefaultChunk = 65536;
 constexpr uint64_t kDefaultBudget = 4ull << 30;
 
 uint64_t now_ns() {
@@ -51,15 +48,7 @@ uint64_t now_ns() {
     return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
-uint64_t round16(uint64_t n) { return (n + 15) & ~15ull; }
-uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
-bool valid_chunk(uint64_t c) { return c >= 16 && c <= (1ull << 30) && (c & (c - 1)) == 0; }
-uint64_t tables_len(uint64_t n, uint64_t nc) { return round16(32 * n + 5 * nc); }
 
-void put32(uint8_t* p, uint32_t v) { memcpy(p, &v, 4); }
-void put64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
-uint32_t get32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
-uint64_t get64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
 
 std::atomic<uint64_t> g_uid{1};
 
@@ -108,14 +97,8 @@ PinnedPool& pool() {
 }  // namespace
 
 // ------------------------------------------------------------ image
-struct ckpt_image {
-    uint8_t* p = nullptr;
-    uint64_t n = 0;
-    uint64_t cap = 0;
-    uint64_t uid = 0;
-};
 
-static ckpt_image* image_new(uint64_t cap) {
+ckpt_image* mk::image_new(uint64_t cap) {
     ckpt_image* im = new ckpt_image();
     uint64_t got = 0;
     im->p = static_cast<uint8_t*>(pool().get(cap, &got));
@@ -183,78 +166,10 @@ int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_table
 
 }  // namespace mk
 
-// ------------------------------------------------------------ device buffers
-namespace {
 
-struct DevBuf {
-    void* p = nullptr;
-    uint64_t cap = 0;
-    hipError_t ensure(uint64_t n) {
-        if (n <= cap) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-            p = nullptr;
-            cap = 0;
-        }
-        uint64_t want = std::max<uint64_t>(n, 256);
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) return e;
-        cap = want;
-        return hipSuccess;
-    }
-    void release() {
-        if (p) hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-    template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
-// A captured single-window dump stage (batched form): replayed whenever the
-// same table shape is dumped again with the same buffers.
-struct GraphEntry {
-    uint64_t key = 0;
-    hipGraphExec_t exec = nullptr;
-    DevBuf descs, dig;
-    uint64_t last_use = 0;
-};
-
-// A resident digest table of an image: its crc[] on the device, kept for
-// later delta dumps taken against that image.
-struct DigestEntry {
-    DevBuf crc;
-    uint64_t n_chunks = 0;
-    uint64_t last_use = 0;
-};
-
-}  // namespace
-
-struct ckpt_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    int num_cu = 0;
-    hipStream_t s_main = nullptr;
-    std::vector<hipStream_t> s_copy;
-    std::mutex mu;
-    uint32_t epoch = 0;
-    uint64_t use_clock = 0;
-    // device buffers
-    DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig;
-    std::map<std::pair<int, uint32_t>, DevBuf> consts;    // (T, C) -> EngineConsts
-    std::map<std::tuple<int, int, int>, int> occ;          // (T, K, mode) -> blocks per CU
-    std::unordered_map<uint64_t, DigestEntry> digests;    // image uid -> resident crc[]
-    std::vector<GraphEntry> graphs;                       // captured dump stages (LRU)
-    std::map<uint64_t, std::pair<ckpt_opts, double>> tuned;  // table shape class -> best options
-    // pinned host scratch for small transfers
-    uint8_t* hsmall = nullptr;
-    uint64_t hsmall_cap = 0;
-    std::vector<hipEvent_t> events;
-    std::vector<hipEvent_t> tevents;                      // timing events (begin, end) per launch
-};
 
 // ------------------------------------------------------------ helpers
-namespace {
+namespace mk {
 
 #define HIPCHK(call)                                 \
     do {                                             \
@@ -495,7 +410,7 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (hipEvent_t e : c->tevents) hipEventDestroy(e);
     DevBuf* bufs[] = {&c->descs, &c->status, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
-                      &c->staging, &c->dig};
+                      &c->staging, &c->dig, &c->amap};
     for (DevBuf* b : bufs) b->release();
     for (auto& kv : c->consts) kv.second.release();
     for (auto& kv : c->digests) kv.second.crc.release();
@@ -511,22 +426,15 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
 // ------------------------------------------------------------ table digests
 // CRC of [AllocRec || crc] (the state digest) and of [kinds || pad] on the
 // device, via the chunk engine in digest mode over two virtual allocations
-// followed by the per-allocation combine. Split in two so that a captured
-// graph can hold the second half: digest_prepare uploads the two virtual
-// descriptors; digest_enqueue only launches kernels and a D2H copy.
-struct DigestPlan {
-    int T = 0, K = 0;
-    const EngineConsts* ec = nullptr;
-    uint64_t nk = 0;
-    uint8_t* base = nullptr;
-    uint64_t off_crc = 0, off_out = 0, off_tk = 0;
-};
-
-static int digest_prepare(ckpt_ctx* c, DevBuf* dig, const uint8_t* recs_crc, uint64_t len_a,
-                          const uint8_t* kinds_pad, uint64_t len_b, DigestPlan* p, ckpt_result* res) {
+// followed by the per-allocation combine. digest_prepare uploads the two
+// virtual descriptors; digest_enqueue only launches kernels and one D2H copy
+// (so a captured graph can hold it).
+hipError_t mk::digest_prepare(ckpt_ctx* c, DevBuf* dig, const uint8_t* recs_crc, uint64_t len_a,
+                              const uint8_t* kinds_pad, uint64_t len_b, DigestPlan* p, hipStream_t s) {
     const uint32_t Cd = 16384;
     pick_tile(Cd, 0, &p->T, &p->K);
-    HIPCHK(get_consts(c, p->T, Cd, &p->ec));
+    hipError_t e = get_consts(c, p->T, Cd, &p->ec);
+    if (e != hipSuccess) return e;
     AllocDesc hd[2];
     const uint64_t nk_a = ceil_div(len_a, Cd), nk_b = ceil_div(len_b, Cd);
     make_desc(&hd[0], 0, recs_crc, len_a, 0, kNoChunk, Cd);
@@ -536,17 +444,17 @@ static int digest_prepare(ckpt_ctx* c, DevBuf* dig, const uint8_t* recs_crc, uin
     p->off_crc = 128;
     p->off_out = p->off_crc + 4 * std::max<uint64_t>(p->nk, 1);
     p->off_tk = p->off_out + 16;
-    HIPCHK(dig->ensure(p->off_tk + 64));
+    if ((e = dig->ensure(p->off_tk + 64)) != hipSuccess) return e;
     p->base = dig->as<uint8_t>();
-    HIPCHK(hipMemcpyAsync(p->base, hd, sizeof(hd), hipMemcpyHostToDevice, c->s_main));
-    return CKPT_OK;
+    return launch_store_descs(reinterpret_cast<AllocDesc*>(p->base), hd[0], hd[1], s);
 }
 
-static int digest_enqueue(ckpt_ctx* c, const DigestPlan& p, uint32_t* out_host /* [2], pinned */,
-                          ckpt_result* res) {
+hipError_t mk::digest_enqueue(ckpt_ctx* c, const DigestPlan& p, uint32_t* out_host /* [2], pinned */,
+                              hipStream_t s) {
     const uint32_t Cd = 16384;
     uint8_t* base = p.base;
-    HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(base + p.off_tk), 0, 1, c->s_main));
+    hipError_t e = launch_fill32(reinterpret_cast<uint32_t*>(base + p.off_tk), 0, 1, s);
+    if (e != hipSuccess) return e;
     if (p.nk) {
         ChunkJob j;
         memset(&j, 0, sizeof(j));
@@ -558,9 +466,9 @@ static int digest_enqueue(ckpt_ctx* c, const DigestPlan& p, uint32_t* out_host /
         j.ec = p.ec;
         j.crc_out = reinterpret_cast<uint32_t*>(base + p.off_crc);
         int grid;
-        HIPCHK(grid_for(c, p.T, p.K, kModeDigest, p.nk, &grid));
-        HIPCHK(launch_chunks(p.T, p.K, kModeDigest, one_job(j, reinterpret_cast<uint32_t*>(base + p.off_tk)), grid,
-                             c->s_main));
+        if ((e = grid_for(c, p.T, p.K, kModeDigest, p.nk, &grid)) != hipSuccess) return e;
+        e = launch_chunks(p.T, p.K, kModeDigest, one_job(j, reinterpret_cast<uint32_t*>(base + p.off_tk)), grid, s);
+        if (e != hipSuccess) return e;
     }
     CombineJob cj;
     memset(&cj, 0, sizeof(cj));
@@ -571,17 +479,46 @@ static int digest_enqueue(ckpt_ctx* c, const DigestPlan& p, uint32_t* out_host /
     cj.ec = p.ec;
     cj.out = reinterpret_cast<uint32_t*>(base + p.off_out);
     cj.mode = kCombineOut;
-    HIPCHK(launch_combine(cj, c->s_main));
-    HIPCHK(hipMemcpyAsync(out_host, base + p.off_out, 8, hipMemcpyDeviceToHost, c->s_main));
-    return CKPT_OK;
+    if ((e = launch_combine(cj, s)) != hipSuccess) return e;
+    return hipMemcpyAsync(out_host, base + p.off_out, 8, hipMemcpyDeviceToHost, s);
 }
 
 static int device_table_digests(ckpt_ctx* c, const uint8_t* recs_crc, uint64_t len_a, const uint8_t* kinds_pad,
                                 uint64_t len_b, uint32_t* out_host /* [2], pinned */, ckpt_result* res) {
     DigestPlan p;
-    int rc = digest_prepare(c, &c->dig, recs_crc, len_a, kinds_pad, len_b, &p, res);
-    if (rc) return rc;
-    return digest_enqueue(c, p, out_host, res);
+    HIPCHK(digest_prepare(c, &c->dig, recs_crc, len_a, kinds_pad, len_b, &p, c->s_main));
+    HIPCHK(digest_enqueue(c, p, out_host, c->s_main));
+    return CKPT_OK;
+}
+
+// ------------------------------------------------------------ resident digest tables
+const uint32_t* mk::digest_lookup(ckpt_ctx* c, uint64_t uid, uint64_t nc) {
+    auto it = c->digests.find(uid);
+    if (it == c->digests.end() || it->second.n_chunks != nc) return nullptr;
+    it->second.last_use = ++c->use_clock;
+    return it->second.crc.as<uint32_t>();
+}
+
+// Keep an image's digest table resident (copied from crc_dev on stream s;
+// the caller synchronizes s before the table is used).
+void mk::digest_insert(ckpt_ctx* c, uint64_t uid, const uint32_t* crc_dev, uint64_t nc, hipStream_t s) {
+    if (!nc) return;
+    if (c->digests.size() >= c->digest_capacity) {
+        auto victim = c->digests.begin();
+        for (auto it = c->digests.begin(); it != c->digests.end(); ++it)
+            if (it->second.last_use < victim->second.last_use) victim = it;
+        victim->second.crc.release();
+        c->digests.erase(victim);
+    }
+    DigestEntry& de = c->digests[uid];
+    if (de.crc.ensure(4 * nc) == hipSuccess &&
+        hipMemcpyAsync(de.crc.p, crc_dev, 4 * nc, hipMemcpyDeviceToDevice, s) == hipSuccess) {
+        de.n_chunks = nc;
+        de.last_use = ++c->use_clock;
+    } else {
+        de.crc.release();
+        c->digests.erase(uid);
+    }
 }
 
 // ------------------------------------------------------------ dump
@@ -669,11 +606,8 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     // resident digest table of the previous image
     const uint32_t* prev_dev = nullptr;
     if (prev && pv.n_chunks) {
-        auto it = c->digests.find(prev->uid);
-        if (it != c->digests.end() && it->second.n_chunks == pv.n_chunks) {
-            prev_dev = it->second.crc.as<uint32_t>();
-            it->second.last_use = ++c->use_clock;
-        } else {
+        prev_dev = digest_lookup(c, prev->uid, pv.n_chunks);
+        if (!prev_dev) {
             HIPCHK(c->prevcrc.ensure(4 * pv.n_chunks));
             HIPCHK(hipMemcpyAsync(c->prevcrc.p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, c->s_main));
             prev_dev = c->prevcrc.as<uint32_t>();
@@ -684,7 +618,9 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     uint32_t* tickets = reinterpret_cast<uint32_t*>(ctl + ctl_tk);
     uint64_t* wtot = reinterpret_cast<uint64_t*>(ctl + ctl_wt);
     uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
+    HIPCHK(c->amap.ensure(4 * std::max<uint64_t>(nc, 1)));
     HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_chunk_map(c->descs.as<AllocDesc>(), n, C, c->amap.as<uint32_t>(), c->s_main));
     HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (ctl_err + 64) / 4, c->s_main));
     // kinds buffer: zero padding after the kinds (the kinds themselves are written by the kernel)
     HIPCHK(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
@@ -726,6 +662,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         j.allocs = c->descs.as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
+        j.amap = c->amap.as<uint32_t>();
         j.g0 = wins[w].g0;
         j.g1 = wins[w].g1;
         j.ec = ec;
@@ -760,7 +697,8 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
         mix(n); mix(C); mix((uint64_t)T); mix((uint64_t)K); mix(nc);
         for (const AllocDesc& x : d) { mix(x.id); mix(x.ptr); mix(x.size); mix(x.prev_first); }
-        const void* ptrs[] = {prev_dev, c->arc.p, c->kinds.p, c->status.p, c->staging.p, c->ctl.p, c->hsmall, ec};
+        const void* ptrs[] = {prev_dev, c->arc.p, c->kinds.p, c->status.p, c->staging.p, c->ctl.p, c->hsmall, ec,
+                              c->amap.p};
         for (const void* q : ptrs) mix(reinterpret_cast<uint64_t>(q));
         GraphEntry* ge = nullptr;
         for (auto& x : c->graphs)
@@ -783,7 +721,8 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             if ((e = hipMemcpy(ge->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
                 return fail(e);
             DigestPlan dp;
-            if (digest_prepare(c, &ge->dig, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, &dp, res)) return fail(hipErrorUnknown);
+            if ((e = digest_prepare(c, &ge->dig, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, &dp, c->s_main)) != hipSuccess)
+                return fail(e);
             int grid, gd;
             if ((e = grid_for(c, T, K, kModeDump, nc, &grid)) != hipSuccess) return fail(e);
             if ((e = grid_for(c, dp.T, dp.K, kModeDigest, std::max<uint64_t>(dp.nk, 1), &gd)) != hipSuccess) return fail(e);
@@ -798,11 +737,13 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             step(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (ctl_err + 64) / 4, c->s_main));
             step(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(len_b, 4), c->s_main));
             step(launch_fill64(c->status.as<uint64_t>(), 0, nc + 64, c->s_main));
+            step(launch_chunk_map(ge->descs.as<AllocDesc>(), n, C, c->amap.as<uint32_t>(), c->s_main));
             ChunkJob j;
             memset(&j, 0, sizeof(j));
             j.allocs = ge->descs.as<AllocDesc>();
             j.n_allocs = n;
             j.C = C;
+            j.amap = c->amap.as<uint32_t>();
             j.g0 = 0;
             j.g1 = nc;
             j.ec = ec;
@@ -826,7 +767,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             gcj.recs = c->arc.as<uint8_t>();
             gcj.mode = kCombineWrite;
             step(launch_combine(gcj, c->s_main));
-            if (digest_enqueue(c, dp, hdig, res)) step(hipErrorUnknown);
+            step(digest_enqueue(c, dp, hdig, c->s_main));
             step(hipMemcpyAsync(hdig + 2, err, 4, hipMemcpyDeviceToHost, c->s_main));
             hipError_t ee = hipStreamEndCapture(c->s_main, &graph);
             if (ce == hipSuccess) ce = ee;
@@ -940,26 +881,8 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     im->n = kHeader + tl + D;
 
     // keep this image's digest table resident for later delta dumps
-    if (nc) {
-        const size_t kMaxEntries = 8;
-        if (c->digests.size() >= kMaxEntries) {
-            auto victim = c->digests.begin();
-            for (auto it = c->digests.begin(); it != c->digests.end(); ++it)
-                if (it->second.last_use < victim->second.last_use) victim = it;
-            victim->second.crc.release();
-            c->digests.erase(victim);
-        }
-        DigestEntry& de = c->digests[im->uid];
-        if (de.crc.ensure(4 * nc) == hipSuccess &&
-            hipMemcpyAsync(de.crc.p, crc_dev, 4 * nc, hipMemcpyDeviceToDevice, c->s_main) == hipSuccess &&
-            hipStreamSynchronize(c->s_main) == hipSuccess) {
-            de.n_chunks = nc;
-            de.last_use = ++c->use_clock;
-        } else {
-            de.crc.release();
-            c->digests.erase(im->uid);
-        }
-    }
+    digest_insert(c, im->uid, crc_dev, nc, c->s_main);
+    if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
     if (res) {
         res->windows = (uint32_t)W;
         res->n_logical = N;
@@ -1059,7 +982,9 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     uint8_t* kind_dev = c->kinds.as<uint8_t>();
 
     // 1) tables up, their digest, payload offsets
+    HIPCHK(c->amap.ensure(4 * std::max<uint64_t>(nc, 1)));
     HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * d.size(), hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_chunk_map(c->descs.as<AllocDesc>(), (uint32_t)d.size(), C, c->amap.as<uint32_t>(), c->s_main));
     HIPCHK(hipMemcpyAsync(c->arc.p, v.recs, len_a, hipMemcpyHostToDevice, c->s_main));
     HIPCHK(hipMemcpyAsync(kind_dev, v.kinds, len_b, hipMemcpyHostToDevice, c->s_main));
     HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, ctl_bad / 4, c->s_main));
@@ -1079,6 +1004,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         oj.allocs = c->descs.as<AllocDesc>();
         oj.n_allocs = v.n_allocs;
         oj.C = C;
+        oj.amap = c->amap.as<uint32_t>();
         oj.n_chunks = nc;
         oj.kind = kind_dev;
         oj.off = c->off.as<uint64_t>();
@@ -1135,6 +1061,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         j.allocs = c->descs.as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
+        j.amap = c->amap.as<uint32_t>();
         j.g0 = 0;
         j.g1 = nc;
         j.ec = ec;
@@ -1173,6 +1100,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         j.allocs = c->descs.as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
+        j.amap = c->amap.as<uint32_t>();
         j.g0 = wins[w].g0;
         j.g1 = wins[w].g1;
         j.ec = ec;

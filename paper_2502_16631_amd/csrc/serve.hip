@@ -1,0 +1,771 @@
+// Served form: a request loop over one context.
+//
+// Requests (dump or restore of one tenant's allocation table) are queued by
+// any thread. A scheduler thread admits them in arrival order while a lane
+// (per-request device buffers) is free and the staging they need (two
+// windows) fits the budget, then drives every admitted request through its
+// windows. Continuous batching: on every tick the next ready window of every
+// active dump request goes into one persistent launch of the chunk engine
+// (a job list, one job per request), and likewise for restores, so requests
+// that arrive while others are on the GPU join the next launch. Each job
+// keeps its own descriptors, tables, staging window and look-back scope, so
+// a request's image is the same whether it runs alone or in a mix.
+//
+// Pipelines per request are those of the plain form (runtime.hip): dump =
+// windows (kernel -> payload length -> D2H copy) then tables and header;
+// restore = validation (tables digest, offsets, counts), a base check for
+// deltas, then windows (H2D copy -> kernel), then the per-allocation check.
+// Tenants' digest tables stay resident in the context (keyed by image) for
+// their incremental dumps.
+#include <hip/hip_runtime.h>
+
+#include <stdlib.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_set>
+
+#include "hostmath.h"
+#include "runtime.h"
+
+using namespace mk;
+
+namespace {
+
+constexpr uint64_t kDefaultSlot = 256ull << 20;
+
+struct Lane {
+    DevBuf descs, arc, kinds, status, ctl, off, wb, staging, dig, prevcrc, amap;
+    uint8_t* hs = nullptr;   // pinned: per-window payload lengths / offsets, digests, flags
+    uint64_t hs_cap = 0;
+    std::vector<hipEvent_t> ev;   // per window: kernel done (dump) or copy done (restore)
+    hipEvent_t slot_ev[2] = {nullptr, nullptr};   // dump: copy of the slot done; restore: kernel done
+    hipEvent_t fin = nullptr;
+    bool busy = false;
+    hipError_t ensure_hs(uint64_t n) {
+        if (n <= hs_cap) return hipSuccess;
+        if (hs) hipHostFree(hs);
+        hs = nullptr;
+        hs_cap = 0;
+        hipError_t e = hipHostMalloc((void**)&hs, n, hipHostMallocDefault);
+        if (e == hipSuccess) hs_cap = n;
+        return e;
+    }
+    hipError_t ensure_events(size_t n) {
+        auto mk_ev = [](hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableTiming); };
+        for (int i = 0; i < 2; ++i)
+            if (!slot_ev[i] && mk_ev(&slot_ev[i]) != hipSuccess) return hipErrorOutOfMemory;
+        if (!fin && mk_ev(&fin) != hipSuccess) return hipErrorOutOfMemory;
+        while (ev.size() < n) {
+            hipEvent_t e;
+            if (mk_ev(&e) != hipSuccess) return hipErrorOutOfMemory;
+            ev.push_back(e);
+        }
+        return hipSuccess;
+    }
+    void release() {
+        DevBuf* b[] = {&descs, &arc, &kinds, &status, &ctl, &off, &wb, &staging, &dig, &prevcrc, &amap};
+        for (DevBuf* x : b) x->release();
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+        for (hipEvent_t e : slot_ev) if (e) hipEventDestroy(e);
+        if (fin) hipEventDestroy(fin);
+        if (hs) hipHostFree(hs);
+    }
+};
+
+enum Phase { kQueued, kValidate, kVerify, kRun, kFinal, kDone };
+
+struct Req {
+    uint64_t ticket = 0;
+    ckpt_request rq{};
+    std::vector<ckpt_alloc> table;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int rc = 0;
+    ckpt_image* out = nullptr;
+    Phase phase = kQueued;
+    bool retired = false;      // done and out of the scheduler's lists: may be polled and freed
+    int lane = -1;
+    // plan
+    uint32_t C = 0;
+    uint32_t n = 0;
+    uint64_t nc = 0, tl = 0, upper = 0, per = 0, W = 0, N = 0;
+    std::vector<AllocDesc> d;
+    const uint32_t* prev_dev = nullptr;
+    uint32_t prev_digest = 0;
+    ImageView v;               // restore: the image
+    // progress
+    uint64_t launched = 0;     // windows whose kernel is enqueued
+    uint64_t staged = 0;       // restore: windows whose H2D copy is enqueued
+    uint64_t copied = 0;       // dump: windows whose D2H copy is enqueued
+    uint64_t pos = 0;          // dump: payload bytes so far
+    uint64_t nu = 0;           // restore: UNCHANGED chunks
+};
+
+}  // namespace
+
+struct ckpt_server {
+    ckpt_ctx* ctx = nullptr;
+    uint32_t max_active = 0;
+    uint64_t budget = 0, slot = kDefaultSlot, reserved = 0;
+    hipStream_t s_dump = nullptr, s_rest = nullptr, s_up = nullptr, s_down = nullptr;
+    DevBuf tickets;                 // shared ticket counters of merged launches
+    uint32_t ticket_next = 0;
+    std::vector<Lane> lanes;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    bool stop = false;
+    std::deque<Req*> pending;
+    std::vector<Req*> active;
+    std::unordered_map<uint64_t, Req*> reqs;   // all not yet polled
+    uint64_t next_ticket = 1;
+    uint64_t in_system = 0;                    // submitted and not completed
+    // stats
+    uint64_t submitted = 0, completed = 0, failed = 0, bytes_logical = 0, bytes_link = 0, launches = 0,
+             max_batch = 0, wait_sum = 0;
+    std::vector<uint64_t> lat;
+};
+
+namespace {
+
+void finish(ckpt_server* s, Req* r, int rc) {
+    r->rc = rc;
+    r->t_done = now_ns();
+    if (rc != CKPT_OK && r->out) {
+        ckpt_image_free(r->out);
+        r->out = nullptr;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    if (r->lane >= 0) {
+        s->lanes[r->lane].busy = false;
+        s->reserved -= 2 * s->slot;
+        r->lane = -1;
+    }
+    s->completed++;
+    if (rc != CKPT_OK) s->failed++;
+    else {
+        s->bytes_logical += r->N;
+        s->bytes_link += kHeader + r->tl + (r->rq.kind == CKPT_REQ_DUMP ? r->pos : r->v.D);
+    }
+    s->lat.push_back(r->t_done - r->t_submit);
+    s->wait_sum += (r->t_admit ? r->t_admit : r->t_done) - r->t_submit;
+    s->in_system--;
+    r->phase = kDone;
+    s->done_cv.notify_all();
+}
+
+uint32_t* next_ticket_slot(ckpt_server* s) {
+    uint32_t* t = s->tickets.as<uint32_t>() + (s->ticket_next % 1024);
+    s->ticket_next++;
+    return t;
+}
+
+#define SCHK(call)                                   \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) { finish(s, r, CKPT_EHIP); return; } \
+    } while (0)
+
+// ---------------------------------------------------------------- admission
+void admit_dump(ckpt_server* s, Req* r) {
+    ckpt_ctx* c = s->ctx;
+    Lane& L = s->lanes[r->lane];
+    r->C = kDefaultChunk;
+    r->n = (uint32_t)r->table.size();
+    std::unordered_set<uint64_t> ids;
+    for (const ckpt_alloc& e : r->table) {
+        if (!ids.insert(e.id).second || (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15)))) {
+            finish(s, r, CKPT_EINVAL);
+            return;
+        }
+    }
+    ImageView pv;
+    std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> pm;
+    if (r->rq.prev) {
+        int rc = parse_image(r->rq.prev->p, r->rq.prev->n, &pv, false);
+        if (rc) { finish(s, r, rc); return; }
+        if (pv.C != r->C) { finish(s, r, CKPT_EINVAL); return; }
+        r->prev_digest = host_crc32c(pv.recs, 32ull * pv.n_allocs + 4 * pv.n_chunks);
+        for (uint64_t a = 0; a < pv.n_allocs; ++a)
+            pm.emplace(get64(pv.recs + 32 * a), std::make_pair(get64(pv.recs + 32 * a + 8), get64(pv.recs + 32 * a + 16)));
+    }
+    r->d.resize(r->n);
+    uint64_t g = 0;
+    for (uint32_t a = 0; a < r->n; ++a) {
+        const ckpt_alloc& e = r->table[a];
+        uint64_t pf = kNoChunk;
+        auto it = pm.find(e.id);
+        if (it != pm.end() && it->second.first == e.size) pf = it->second.second;
+        make_desc(&r->d[a], e.id, e.dev_ptr, e.size, g, pf, r->C);
+        const uint64_t nk = ceil_div(e.size, r->C);
+        g += nk;
+        r->N += e.size;
+        if (nk) r->upper += (nk - 1) * r->C + round16(r->d[a].tail_len);
+    }
+    r->nc = g;
+    r->tl = tables_len(r->n, r->nc);
+    r->per = s->slot / r->C;
+    r->W = ceil_div(r->nc, r->per);
+    SCHK(L.descs.ensure(sizeof(AllocDesc) * std::max<uint32_t>(r->n, 1)));
+    SCHK(L.arc.ensure(r->tl + 16));
+    SCHK(L.kinds.ensure(r->tl + 16));
+    SCHK(L.status.ensure(8 * (r->per + 64)));
+    SCHK(L.ctl.ensure(16 * (r->W + 2) + 64));
+    SCHK(L.staging.ensure(2 * s->slot));
+    SCHK(L.ensure_hs(8 * (r->W + 2) + 64));
+    SCHK(L.ensure_events(r->W + 1));
+    r->out = image_new(kHeader + r->tl + r->upper);
+    if (!r->out) { finish(s, r, CKPT_ENOMEM); return; }
+    if (r->rq.prev && pv.n_chunks) {
+        r->prev_dev = digest_lookup(c, r->rq.prev->uid, pv.n_chunks);
+        if (!r->prev_dev) {
+            SCHK(L.prevcrc.ensure(4 * pv.n_chunks));
+            SCHK(hipMemcpyAsync(L.prevcrc.p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, s->s_dump));
+            r->prev_dev = L.prevcrc.as<uint32_t>();
+        }
+    }
+    SCHK(L.amap.ensure(4 * std::max<uint64_t>(r->nc, 1)));
+    SCHK(hipMemcpyAsync(L.descs.p, r->d.data(), sizeof(AllocDesc) * r->n, hipMemcpyHostToDevice, s->s_dump));
+    SCHK(launch_chunk_map(L.descs.as<AllocDesc>(), r->n, r->C, L.amap.as<uint32_t>(), s->s_dump));
+    SCHK(launch_fill32(L.ctl.as<uint32_t>(), 0, (16 * (r->W + 2) + 64) / 4, s->s_dump));
+    SCHK(launch_fill32(L.kinds.as<uint32_t>(), 0, ceil_div(r->tl - 32ull * r->n - 4 * r->nc, 4), s->s_dump));
+    r->phase = kRun;
+}
+
+void admit_restore(ckpt_server* s, Req* r) {
+    ckpt_ctx* c = s->ctx;
+    Lane& L = s->lanes[r->lane];
+    int rc = parse_image(r->rq.img->p, r->rq.img->n, &r->v, false);
+    if (rc) { finish(s, r, rc); return; }
+    const ImageView& v = r->v;
+    r->C = v.C;
+    r->n = (uint32_t)r->table.size();
+    r->nc = v.n_chunks;
+    r->tl = v.tl;
+    r->N = v.N;
+    for (uint32_t a = 0; a < r->n && a < v.n_allocs; ++a) {
+        const ckpt_alloc& e = r->table[a];
+        if (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15))) { finish(s, r, CKPT_EINVAL); return; }
+    }
+    r->d.resize(v.n_allocs);
+    for (uint64_t a = 0; a < v.n_allocs; ++a) {
+        const uint8_t* rec = v.recs + 32 * a;
+        make_desc(&r->d[a], get64(rec), a < r->n ? r->table[a].dev_ptr : nullptr, get64(rec + 8), get64(rec + 16),
+                  kNoChunk, r->C);
+    }
+    r->per = std::max<uint64_t>(1, s->slot / r->C);
+    r->W = ceil_div(std::max<uint64_t>(r->nc, 1), r->per);
+    const uint64_t len_a = 32ull * v.n_allocs + 4 * v.n_chunks, len_b = v.tl - len_a;
+    SCHK(L.descs.ensure(sizeof(AllocDesc) * std::max<uint64_t>(v.n_allocs, 1)));
+    SCHK(L.arc.ensure(v.tl + 16));
+    SCHK(L.kinds.ensure(v.tl + 16));
+    SCHK(L.off.ensure(8 * std::max<uint64_t>(v.n_chunks, 1)));
+    SCHK(L.wb.ensure(8 * (r->W + 2)));
+    SCHK(L.status.ensure(8 * (ceil_div(v.n_chunks, 256) + 64)));
+    // ctl: [0] offsets ticket | [8] counts[4] | [40] bad | [48] bad2 | [56] err | [64..] window tickets
+    SCHK(L.ctl.ensure(64 + 4 * (r->W + 4)));
+    SCHK(L.staging.ensure(2 * s->slot));
+    SCHK(L.ensure_hs(128 + 8 * (r->W + 2)));
+    SCHK(L.ensure_events(r->W + 1));
+    uint8_t* ctl = L.ctl.as<uint8_t>();
+    hipStream_t st = s->s_rest;
+    SCHK(L.amap.ensure(4 * std::max<uint64_t>(v.n_chunks, 1)));
+    SCHK(hipMemcpyAsync(L.descs.p, r->d.data(), sizeof(AllocDesc) * r->d.size(), hipMemcpyHostToDevice, st));
+    SCHK(launch_chunk_map(L.descs.as<AllocDesc>(), (uint32_t)r->d.size(), r->C, L.amap.as<uint32_t>(), st));
+    SCHK(hipMemcpyAsync(L.arc.p, v.recs, len_a, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(L.kinds.p, v.kinds, len_b, hipMemcpyHostToDevice, st));
+    SCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (64 + 4 * (r->W + 4)) / 4, st));
+    SCHK(launch_fill64(reinterpret_cast<uint64_t*>(ctl + 40), ~0ull, 2, st));
+    DigestPlan dp;
+    SCHK(digest_prepare(c, &L.dig, L.arc.as<uint8_t>(), len_a, L.kinds.as<uint8_t>(), len_b, &dp, st));
+    SCHK(digest_enqueue(c, dp, reinterpret_cast<uint32_t*>(L.hs), st));
+    if (v.n_chunks) {
+        bool wrapped;
+        const uint32_t ep = next_epoch(c, &wrapped);
+        if (wrapped) SCHK(launch_fill64(L.status.as<uint64_t>(), 0, L.status.cap / 8, st));
+        OffJob oj;
+        memset(&oj, 0, sizeof(oj));
+        oj.allocs = L.descs.as<AllocDesc>();
+        oj.n_allocs = v.n_allocs;
+        oj.C = r->C;
+        oj.amap = L.amap.as<uint32_t>();
+        oj.n_chunks = v.n_chunks;
+        oj.kind = L.kinds.as<uint8_t>();
+        oj.off = L.off.as<uint64_t>();
+        oj.per_window = r->per;
+        oj.wb = L.wb.as<uint64_t>();
+        oj.n_windows = r->W;
+        oj.status = L.status.as<uint64_t>();
+        oj.ticket = reinterpret_cast<uint32_t*>(ctl);
+        oj.counts = reinterpret_cast<unsigned long long*>(ctl + 8);
+        oj.err = reinterpret_cast<uint32_t*>(ctl + 56);
+        oj.epoch = ep;
+        SCHK(launch_offsets(oj, (int)std::min<uint64_t>(ceil_div(v.n_chunks, 256), 8ull * c->num_cu), st));
+        SCHK(hipMemcpyAsync(L.hs + 128, L.wb.p, 8 * (r->W + 1), hipMemcpyDeviceToHost, st));
+    }
+    SCHK(hipMemcpyAsync(L.hs + 16, ctl + 8, 32, hipMemcpyDeviceToHost, st));
+    SCHK(hipEventRecord(L.fin, st));
+    r->phase = kValidate;
+}
+
+// ---------------------------------------------------------------- restore checks
+void restore_validated(ckpt_server* s, Req* r) {
+    ckpt_ctx* c = s->ctx;
+    Lane& L = s->lanes[r->lane];
+    const ImageView& v = r->v;
+    const uint32_t* dig = reinterpret_cast<const uint32_t*>(L.hs);
+    const uint64_t* cnt = reinterpret_cast<const uint64_t*>(L.hs + 16);
+    const uint64_t len_a = 32ull * v.n_allocs + 4 * v.n_chunks, len_b = v.tl - len_a;
+    if (crc_combine(dig[0], dig[1], len_b) != v.tables_crc) { finish(s, r, CKPT_ECORRUPT); return; }
+    const uint64_t nz = cnt[0], nd = cnt[1], nu = cnt[2], ninv = cnt[3];
+    if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != v.n_chunks) { finish(s, r, CKPT_ECORRUPT); return; }
+    const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
+    if ((v.n_chunks ? wb[r->W] : 0) != v.D) { finish(s, r, CKPT_ECORRUPT); return; }
+    if (v.n_allocs != r->n) { finish(s, r, CKPT_EMISMATCH); return; }
+    for (uint32_t a = 0; a < r->n; ++a)
+        if (r->table[a].id != r->d[a].id || r->table[a].size != r->d[a].size) { finish(s, r, CKPT_EMISMATCH); return; }
+    r->nu = nu;
+    if (nu) {
+        int T, K;
+        pick_tile(r->C, 0, &T, &K);
+        const EngineConsts* ec;
+        SCHK(get_consts(c, T, r->C, &ec));
+        uint8_t* ctl = L.ctl.as<uint8_t>();
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = L.descs.as<AllocDesc>();
+        j.n_allocs = r->n;
+        j.C = r->C;
+        j.amap = L.amap.as<uint32_t>();
+        j.g0 = 0;
+        j.g1 = r->nc;
+        j.ec = ec;
+        j.kind_in = L.kinds.as<uint8_t>();
+        j.ref_crc = reinterpret_cast<const uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
+        j.bad = reinterpret_cast<unsigned long long*>(ctl + 40);
+        j.err = reinterpret_cast<uint32_t*>(ctl + 56);
+        int grid;
+        SCHK(grid_for(c, T, K, kModeVerify, r->nc, &grid));
+        uint32_t* tk = next_ticket_slot(s);
+        SCHK(launch_fill32(tk, 0, 1, s->s_rest));
+        SCHK(launch_chunks(T, K, kModeVerify, one_job(j, tk), grid, s->s_rest));
+        SCHK(hipMemcpyAsync(L.hs + 64, ctl + 40, 8, hipMemcpyDeviceToHost, s->s_rest));
+        SCHK(hipEventRecord(L.fin, s->s_rest));
+        r->phase = kVerify;
+        return;
+    }
+    r->phase = kRun;
+}
+
+// ---------------------------------------------------------------- merged launches
+// One launch per mode over the next ready window of every active request.
+void launch_merged(ckpt_server* s, bool dump) {
+    ckpt_ctx* c = s->ctx;
+    std::vector<Req*> batch;
+    for (Req* r : s->active) {
+        if (r->phase != kRun || (r->rq.kind == CKPT_REQ_DUMP) != dump || r->launched >= r->W) continue;
+        Lane& L = s->lanes[r->lane];
+        const uint64_t w = r->launched;
+        if (dump) {
+            // at most two windows in flight: slot w%2 must have been copied out
+            if (w >= 2 && (r->copied < w - 1 || hipEventQuery(L.slot_ev[w % 2]) != hipSuccess)) continue;
+        } else {
+            if (r->staged <= w || hipEventQuery(L.ev[w]) != hipSuccess) continue;   // payload not up yet
+        }
+        if (r->nc == 0) { r->launched = r->W; continue; }
+        batch.push_back(r);
+        if (batch.size() == (size_t)kMaxJobs) break;
+    }
+    if (batch.empty()) return;
+    // group by chunk size: the first request's chunk size goes now
+    const uint32_t C = batch[0]->C;
+    int T, K;
+    pick_tile(C, 0, &T, &K);
+    const EngineConsts* ec;
+    if (get_consts(c, T, C, &ec) != hipSuccess) return;
+    hipStream_t st = dump ? s->s_dump : s->s_rest;
+    JobList jl;
+    memset(&jl, 0, sizeof(jl));
+    std::vector<Req*> used;
+    uint64_t total = 0;
+    for (Req* r : batch) {
+        if (r->C != C) continue;
+        Lane& L = s->lanes[r->lane];
+        const uint64_t w = r->launched;
+        ChunkJob& j = jl.job[jl.n_jobs];
+        memset(&j, 0, sizeof(j));
+        j.allocs = L.descs.as<AllocDesc>();
+        j.n_allocs = r->n;
+        j.C = C;
+        j.amap = L.amap.as<uint32_t>();
+        j.g0 = w * r->per;
+        j.g1 = std::min(r->nc, (w + 1) * r->per);
+        j.ec = ec;
+        uint8_t* slotp = L.staging.as<uint8_t>() + (w % 2) * s->slot;
+        j.slot = slotp;
+        if (dump) {
+            bool wrapped;
+            j.epoch = next_epoch(c, &wrapped);
+            if (wrapped) launch_fill64(L.status.as<uint64_t>(), 0, L.status.cap / 8, st);
+            j.crc_out = reinterpret_cast<uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
+            j.kind_out = L.kinds.as<uint8_t>();
+            j.prev_crc = r->prev_dev;
+            j.status = L.status.as<uint64_t>();
+            j.wtotal = reinterpret_cast<uint64_t*>(L.ctl.as<uint8_t>()) + w;
+            j.err = reinterpret_cast<uint32_t*>(L.ctl.as<uint8_t>() + 16 * (r->W + 2));
+            // the slot's previous copy must be finished before it is overwritten
+            if (w >= 2) hipStreamWaitEvent(st, L.slot_ev[w % 2], 0);
+        } else {
+            uint8_t* ctl = L.ctl.as<uint8_t>();
+            const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
+            j.kind_in = L.kinds.as<uint8_t>();
+            j.ref_crc = reinterpret_cast<const uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
+            j.off = L.off.as<uint64_t>();
+            j.slot_base = wb[w];
+            j.bad = reinterpret_cast<unsigned long long*>(ctl + 40);
+            j.err = reinterpret_cast<uint32_t*>(ctl + 56);
+            hipStreamWaitEvent(st, L.ev[w], 0);   // payload copy of this window
+        }
+        jl.prefix[jl.n_jobs] = total;
+        total += j.g1 - j.g0;
+        jl.n_jobs++;
+        used.push_back(r);
+    }
+    jl.prefix[jl.n_jobs] = total;
+    uint32_t* tk = next_ticket_slot(s);
+    jl.ticket = tk;
+    int grid;
+    hipError_t e = launch_fill32(tk, 0, 1, st);
+    if (e == hipSuccess) e = grid_for(c, T, K, dump ? kModeDump : kModeRestore, total, &grid);
+    if (e == hipSuccess) e = launch_chunks(T, K, dump ? kModeDump : kModeRestore, jl, grid, st);
+    for (Req* r : used) {
+        Lane& L = s->lanes[r->lane];
+        const uint64_t w = r->launched;
+        if (e == hipSuccess && dump)
+            e = hipMemcpyAsync(L.hs + 8 * w, L.ctl.as<uint64_t>() + w, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(dump ? L.ev[w] : L.slot_ev[w % 2], st);
+        r->launched++;
+    }
+    s->launches++;
+    s->max_batch = std::max<uint64_t>(s->max_batch, used.size());
+    if (e != hipSuccess)
+        for (Req* r : used) finish(s, r, CKPT_EHIP);
+}
+
+// ---------------------------------------------------------------- per-request progress
+void progress_dump(ckpt_server* s, Req* r) {
+    ckpt_ctx* c = s->ctx;
+    Lane& L = s->lanes[r->lane];
+    // copy out finished windows, in order
+    while (r->copied < r->launched && hipEventQuery(L.ev[r->copied]) == hipSuccess) {
+        const uint64_t w = r->copied;
+        const uint64_t dw = reinterpret_cast<const uint64_t*>(L.hs)[w];
+        if (dw > s->slot || r->pos + dw > r->upper) { finish(s, r, CKPT_EHIP); return; }
+        SCHK(hipStreamWaitEvent(s->s_down, L.ev[w], 0));
+        if (dw)
+            SCHK(hipMemcpyAsync(r->out->p + kHeader + r->tl + r->pos, L.staging.as<uint8_t>() + (w % 2) * s->slot, dw,
+                                hipMemcpyDeviceToHost, s->s_down));
+        SCHK(hipEventRecord(L.slot_ev[w % 2], s->s_down));
+        r->pos += dw;
+        r->copied++;
+    }
+    if (r->phase == kRun && r->copied == r->W) {
+        // tables: per-allocation CRCs, digests, copy-out
+        int T, K;
+        pick_tile(r->C, 0, &T, &K);
+        const EngineConsts* ec;
+        SCHK(get_consts(c, T, r->C, &ec));
+        uint32_t* crc_dev = reinterpret_cast<uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
+        CombineJob cj;
+        memset(&cj, 0, sizeof(cj));
+        cj.allocs = L.descs.as<AllocDesc>();
+        cj.n_allocs = r->n;
+        cj.C = r->C;
+        cj.crc = crc_dev;
+        cj.ec = ec;
+        cj.recs = L.arc.as<uint8_t>();
+        cj.mode = kCombineWrite;
+        SCHK(launch_combine(cj, s->s_dump));
+        const uint64_t len_a = 32ull * r->n + 4 * r->nc, len_b = r->tl - len_a;
+        uint32_t* hdig = reinterpret_cast<uint32_t*>(L.hs + 8 * (r->W + 1));
+        DigestPlan dp;
+        SCHK(digest_prepare(c, &L.dig, L.arc.as<uint8_t>(), len_a, L.kinds.as<uint8_t>(), len_b, &dp, s->s_dump));
+        SCHK(digest_enqueue(c, dp, hdig, s->s_dump));
+        SCHK(hipMemcpyAsync(r->out->p + kHeader, L.arc.p, len_a, hipMemcpyDeviceToHost, s->s_dump));
+        SCHK(hipMemcpyAsync(r->out->p + kHeader + len_a, L.kinds.p, len_b, hipMemcpyDeviceToHost, s->s_dump));
+        SCHK(hipMemcpyAsync(hdig + 2, L.ctl.as<uint8_t>() + 16 * (r->W + 2), 4, hipMemcpyDeviceToHost, s->s_dump));
+        digest_insert(c, r->out->uid, crc_dev, r->nc, s->s_dump);
+        SCHK(hipEventRecord(L.fin, s->s_dump));
+        r->phase = kFinal;
+        return;
+    }
+    if (r->phase == kFinal && hipEventQuery(L.fin) == hipSuccess) {
+        if (r->W && hipEventQuery(L.slot_ev[(r->W - 1) % 2]) != hipSuccess) return;
+        if (r->W > 1 && hipEventQuery(L.slot_ev[(r->W - 2) % 2]) != hipSuccess) return;
+        const uint32_t* hdig = reinterpret_cast<const uint32_t*>(L.hs + 8 * (r->W + 1));
+        if (hdig[2]) { finish(s, r, CKPT_EHIP); return; }
+        const uint64_t len_a = 32ull * r->n + 4 * r->nc, len_b = r->tl - len_a;
+        uint8_t* h = r->out->p;
+        memcpy(h, "MICKPT01", 8);
+        put32(h + 8, 1);
+        put32(h + 12, r->rq.prev ? 1u : 0u);
+        put32(h + 16, r->C);
+        put32(h + 20, r->n);
+        put64(h + 24, r->nc);
+        put64(h + 32, r->pos);
+        put32(h + 40, r->rq.prev ? r->prev_digest : 0u);
+        put32(h + 44, 0);
+        put64(h + 48, r->N);
+        put32(h + 56, crc_combine(hdig[0], hdig[1], len_b));
+        put32(h + 60, host_crc32c(h, 60));
+        r->out->n = kHeader + r->tl + r->pos;
+        finish(s, r, CKPT_OK);
+    }
+}
+
+void progress_restore(ckpt_server* s, Req* r) {
+    ckpt_ctx* c = s->ctx;
+    Lane& L = s->lanes[r->lane];
+    if (r->phase == kValidate) {
+        if (hipEventQuery(L.fin) != hipSuccess) return;
+        restore_validated(s, r);
+        return;
+    }
+    if (r->phase == kVerify) {
+        if (hipEventQuery(L.fin) != hipSuccess) return;
+        const uint64_t bad = *reinterpret_cast<const uint64_t*>(L.hs + 64);
+        if (bad != kNoChunk) { finish(s, r, CKPT_EBASE); return; }
+        r->phase = kRun;
+        return;
+    }
+    if (r->phase == kRun) {
+        // stage payload windows ahead of the kernels: two slots
+        const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
+        while (r->staged < r->W && r->staged < r->launched + 2) {
+            const uint64_t w = r->staged;
+            if (w >= 2) {
+                if (r->launched < w - 1) break;
+                SCHK(hipStreamWaitEvent(s->s_up, L.slot_ev[w % 2], 0));   // kernel of window w-2 done
+            }
+            const uint64_t len = r->nc ? wb[w + 1] - wb[w] : 0;
+            if (len > s->slot) { finish(s, r, CKPT_ECORRUPT); return; }
+            if (len)
+                SCHK(hipMemcpyAsync(L.staging.as<uint8_t>() + (w % 2) * s->slot, r->v.payload + wb[w], len,
+                                    hipMemcpyHostToDevice, s->s_up));
+            SCHK(hipEventRecord(L.ev[w], s->s_up));
+            r->staged++;
+        }
+        if (r->launched == r->W) {
+            int T, K;
+            pick_tile(r->C, 0, &T, &K);
+            const EngineConsts* ec;
+            SCHK(get_consts(c, T, r->C, &ec));
+            uint8_t* ctl = L.ctl.as<uint8_t>();
+            CombineJob cj;
+            memset(&cj, 0, sizeof(cj));
+            cj.allocs = L.descs.as<AllocDesc>();
+            cj.n_allocs = r->n;
+            cj.C = r->C;
+            cj.crc = reinterpret_cast<const uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
+            cj.ec = ec;
+            cj.recs = L.arc.as<uint8_t>();
+            cj.bad = reinterpret_cast<unsigned long long*>(ctl + 48);
+            cj.mode = kCombineCheck;
+            SCHK(launch_combine(cj, s->s_rest));
+            SCHK(hipMemcpyAsync(L.hs + 64, ctl + 40, 24, hipMemcpyDeviceToHost, s->s_rest));
+            SCHK(hipEventRecord(L.fin, s->s_rest));
+            r->phase = kFinal;
+        }
+        return;
+    }
+    if (r->phase == kFinal) {
+        if (hipEventQuery(L.fin) != hipSuccess) return;
+        const uint64_t* q = reinterpret_cast<const uint64_t*>(L.hs + 64);
+        if ((uint32_t)q[2]) { finish(s, r, CKPT_EHIP); return; }
+        if (q[0] != kNoChunk || q[1] != kNoChunk) { finish(s, r, CKPT_ECORRUPT); return; }
+        finish(s, r, CKPT_OK);
+    }
+}
+
+void loop(ckpt_server* s) {
+    hipSetDevice(s->ctx->device);
+    for (;;) {
+        std::vector<Req*> fresh;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            if (s->active.empty() && s->pending.empty())
+                s->cv.wait(g, [s] { return s->stop || !s->pending.empty(); });
+            if (s->stop && s->active.empty() && s->pending.empty()) return;
+            // admission: arrival order, a free lane and two staging windows of budget
+            const uint64_t now = now_ns();
+            while (!s->pending.empty()) {
+                Req* r = s->pending.front();
+                if (r->rq.deadline_ns && now > r->rq.deadline_ns) {
+                    s->pending.pop_front();
+                    fresh.push_back(r);   // finished below as timed out
+                    continue;
+                }
+                if (s->active.size() >= s->max_active || s->reserved + 2 * s->slot > s->budget) break;
+                int lane = -1;
+                for (size_t i = 0; i < s->lanes.size(); ++i)
+                    if (!s->lanes[i].busy) { lane = (int)i; break; }
+                if (lane < 0) break;
+                s->pending.pop_front();
+                s->lanes[lane].busy = true;
+                s->reserved += 2 * s->slot;
+                r->lane = lane;
+                r->t_admit = now;
+                s->active.push_back(r);
+                fresh.push_back(r);
+            }
+        }
+        std::lock_guard<std::mutex> cg(s->ctx->mu);
+        for (Req* r : fresh) {
+            if (r->lane < 0) {
+                finish(s, r, CKPT_ETIMEOUT);
+                std::lock_guard<std::mutex> g(s->mu);
+                r->retired = true;
+                continue;
+            }
+            if (r->rq.kind == CKPT_REQ_DUMP) admit_dump(s, r);
+            else admit_restore(s, r);
+        }
+        for (Req* r : s->active) {
+            if (r->phase == kDone) continue;
+            if (r->rq.kind == CKPT_REQ_DUMP) progress_dump(s, r);
+            else progress_restore(s, r);
+        }
+        launch_merged(s, true);
+        launch_merged(s, false);
+        for (Req* r : s->active) {
+            if (r->phase == kDone) continue;
+            if (r->rq.kind == CKPT_REQ_DUMP) progress_dump(s, r);
+            else progress_restore(s, r);
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (Req* r : s->active)
+                if (r->phase == kDone) r->retired = true;
+            s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                           [](Req* r) { return r->phase == kDone; }),
+                            s->active.end());
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" int ckpt_serve_create(ckpt_ctx* ctx, uint32_t max_active, uint64_t budget, ckpt_server** out) {
+    if (!ctx || !out) return CKPT_EINVAL;
+    *out = nullptr;
+    if (max_active == 0 || max_active > (uint32_t)kMaxJobs) max_active = kMaxJobs;
+    ckpt_server* s = new ckpt_server();
+    s->ctx = ctx;
+    s->max_active = max_active;
+    s->budget = budget ? budget : ctx->budget;
+    if (const char* env = getenv("MICKPT_SERVE_WINDOW")) s->slot = std::max<uint64_t>(strtoull(env, nullptr, 0), 1 << 20);
+    s->slot = s->slot / kDefaultChunk * kDefaultChunk;
+    if (s->budget < 2 * s->slot) { delete s; return CKPT_ENOMEM; }
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->digest_capacity = std::max<size_t>(ctx->digest_capacity, 128);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) { delete s; return CKPT_EHIP; }
+    hipStream_t* ss[] = {&s->s_dump, &s->s_rest, &s->s_up, &s->s_down};
+    for (hipStream_t* p : ss)
+        if (hipStreamCreateWithFlags(p, hipStreamNonBlocking) != hipSuccess) { delete s; return CKPT_EHIP; }
+    if (s->tickets.ensure(4 * 1024) != hipSuccess) { delete s; return CKPT_ENOMEM; }
+    s->lanes.resize(max_active);
+    s->th = std::thread(loop, s);
+    *out = s;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_serve_submit(ckpt_server* s, const ckpt_request* rq, uint64_t* ticket) {
+    if (!s || !rq || !ticket || !rq->table || (rq->table->n && !rq->table->v)) return CKPT_EINVAL;
+    if (rq->kind != CKPT_REQ_DUMP && rq->kind != CKPT_REQ_RESTORE) return CKPT_EINVAL;
+    if (rq->kind == CKPT_REQ_RESTORE && !rq->img) return CKPT_EINVAL;
+    Req* r = new Req();
+    r->rq = *rq;
+    r->table.assign(rq->table->v, rq->table->v + rq->table->n);
+    r->t_submit = now_ns();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        r->ticket = s->next_ticket++;
+        s->reqs[r->ticket] = r;
+        s->pending.push_back(r);
+        s->submitted++;
+        s->in_system++;
+        *ticket = r->ticket;
+    }
+    s->cv.notify_one();
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_serve_poll(ckpt_server* s, uint64_t ticket, int* rc, ckpt_image** out, uint64_t* latency_ns) {
+    if (!s) return CKPT_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return CKPT_EINVAL;
+    Req* r = it->second;
+    if (r->phase != kDone || !r->retired) return 0;
+    if (rc) *rc = r->rc;
+    if (out) *out = r->out;
+    else if (r->out) ckpt_image_free(r->out);
+    if (latency_ns) *latency_ns = r->t_done - r->t_submit;
+    s->reqs.erase(it);
+    delete r;
+    return 1;
+}
+
+extern "C" int ckpt_serve_drain(ckpt_server* s) {
+    if (!s) return CKPT_EINVAL;
+    std::unique_lock<std::mutex> g(s->mu);
+    s->done_cv.wait(g, [s] { return s->in_system == 0; });
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_serve_stats(ckpt_server* s, ckpt_server_stats* st) {
+    if (!s || !st) return CKPT_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    memset(st, 0, sizeof(*st));
+    st->submitted = s->submitted;
+    st->completed = s->completed;
+    st->failed = s->failed;
+    st->bytes_logical = s->bytes_logical;
+    st->bytes_link = s->bytes_link;
+    st->launches = s->launches;
+    st->max_batch = s->max_batch;
+    if (!s->lat.empty()) {
+        std::vector<uint64_t> l = s->lat;
+        std::sort(l.begin(), l.end());
+        auto q = [&l](double p) { return l[std::min(l.size() - 1, (size_t)(p * (l.size() - 1) + 0.5))]; };
+        st->p50_ns = q(0.50);
+        st->p99_ns = q(0.99);
+        st->mean_wait_ns = s->wait_sum / s->lat.size();
+    }
+    return CKPT_OK;
+}
+
+extern "C" void ckpt_serve_destroy(ckpt_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    hipStream_t ss[] = {s->s_dump, s->s_rest, s->s_up, s->s_down};
+    for (hipStream_t x : ss)
+        if (x) { hipStreamSynchronize(x); hipStreamDestroy(x); }
+    for (Lane& L : s->lanes) L.release();
+    s->tickets.release();
+    for (auto& kv : s->reqs) {
+        if (kv.second->out) ckpt_image_free(kv.second->out);
+        delete kv.second;
+    }
+    delete s;
+}

@@ -62,6 +62,22 @@ class ckpt_result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class ckpt_request(ctypes.Structure):
+    _fields_ = [("kind", _u32), ("tenant", _u32), ("table", ctypes.POINTER(ckpt_alloc_table)),
+                ("prev", ctypes.c_void_p), ("img", ctypes.c_void_p), ("deadline_ns", _u64)]
+
+
+class ckpt_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("failed", _u64), ("bytes_logical", _u64),
+                ("bytes_link", _u64), ("launches", _u64), ("max_batch", _u64), ("p50_ns", _u64),
+                ("p99_ns", _u64), ("mean_wait_ns", _u64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+REQ_DUMP = 1
+REQ_RESTORE = 2
 _lib = None
 
 
@@ -97,6 +113,19 @@ def lib():
         L.ckpt_autotune.argtypes = [vp, ctypes.POINTER(ckpt_alloc_table), _u64, _u32, ctypes.POINTER(ckpt_opts),
                                     ctypes.POINTER(ctypes.c_double)]
         L.ckpt_autotune.restype = ctypes.c_int
+        L.ckpt_serve_create.argtypes = [vp, _u32, _u64, ctypes.POINTER(vp)]
+        L.ckpt_serve_create.restype = ctypes.c_int
+        L.ckpt_serve_submit.argtypes = [vp, ctypes.POINTER(ckpt_request), ctypes.POINTER(_u64)]
+        L.ckpt_serve_submit.restype = ctypes.c_int
+        L.ckpt_serve_poll.argtypes = [vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
+                                      ctypes.POINTER(_u64)]
+        L.ckpt_serve_poll.restype = ctypes.c_int
+        L.ckpt_serve_drain.argtypes = [vp]
+        L.ckpt_serve_drain.restype = ctypes.c_int
+        L.ckpt_serve_stats.argtypes = [vp, ctypes.POINTER(ckpt_server_stats)]
+        L.ckpt_serve_stats.restype = ctypes.c_int
+        L.ckpt_serve_destroy.argtypes = [vp]
+        L.ckpt_serve_destroy.restype = None
         L.ckpt_crc32c.argtypes = [vp, _u64]
         L.ckpt_crc32c.restype = _u32
         _lib = L
@@ -234,3 +263,62 @@ def ckpt_image_import(data):
     out = ctypes.c_void_p()
     rc = lib().ckpt_image_import(a.ctypes.data if a.size else None, a.size, ctypes.byref(out))
     return rc, (Image(out.value) if rc == 0 else None)
+
+
+class _Pending:
+    """A submitted request's marshalled arguments, kept alive until it is polled."""
+
+    def __init__(self, tab, keep, req):
+        self.tab, self.keep, self.req = tab, keep, req
+
+
+_inflight = {}
+
+
+def ckpt_serve_create(ctx, max_active=0, budget=0):
+    srv = ctypes.c_void_p()
+    rc = lib().ckpt_serve_create(ctx, int(max_active), int(budget), ctypes.byref(srv))
+    if rc != 0:
+        raise RuntimeError("ckpt_serve_create: %s" % ckpt_strerror(rc))
+    return srv
+
+
+def ckpt_serve_submit(srv, kind, table, prev=None, img=None, tenant=0, deadline_ns=0):
+    tab, keep = _table(table)
+    req = ckpt_request(kind, tenant, ctypes.pointer(tab), prev.handle if prev is not None else None,
+                       img.handle if img is not None else None, deadline_ns)
+    ticket = _u64()
+    rc = lib().ckpt_serve_submit(srv, ctypes.byref(req), ctypes.byref(ticket))
+    if rc == 0:
+        _inflight[(srv.value, ticket.value)] = _Pending(tab, keep, req)
+    return rc, ticket.value
+
+
+def ckpt_serve_poll(srv, ticket):
+    """Returns (done, rc, Image|None, latency_ns)."""
+    rc = ctypes.c_int(0)
+    out = ctypes.c_void_p()
+    lat = _u64()
+    done = lib().ckpt_serve_poll(srv, ticket, ctypes.byref(rc), ctypes.byref(out), ctypes.byref(lat))
+    if done == 1:
+        _inflight.pop((srv.value, ticket), None)
+        return True, rc.value, (Image(out.value) if out.value else None), lat.value
+    if done < 0:
+        raise RuntimeError("ckpt_serve_poll: %s" % ckpt_strerror(done))
+    return False, None, None, None
+
+
+def ckpt_serve_drain(srv):
+    return lib().ckpt_serve_drain(srv)
+
+
+def ckpt_serve_stats(srv):
+    st = ckpt_server_stats()
+    lib().ckpt_serve_stats(srv, ctypes.byref(st))
+    return st
+
+
+def ckpt_serve_destroy(srv):
+    lib().ckpt_serve_destroy(srv)
+    for k in [k for k in _inflight if k[0] == srv.value]:
+        _inflight.pop(k)
