@@ -77,7 +77,7 @@ def incremental(args, torch, mk, link):
         "delta_dump_ms_p50": round(_pct(t_delta, 50) * 1e3, 2),
         "base_restore_ms_p50": round(_pct(t_base, 50) * 1e3, 2),
         "delta_apply_ms_p50": round(_pct(t_apply, 50) * 1e3, 2),
-        "delta_link_GBps": round((D + info["link_bytes"] - D) / td / 1e9, 2),
+        "delta_link_GBps": round(info["link_bytes"] / td / 1e9, 2),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
         "roofline": {"bound": "hbm", "achieved": round(alg / k_avg / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(alg / k_avg / 1e9 / 8000.0, 4), "kernel": "k_chunks dump mode (delta)"},

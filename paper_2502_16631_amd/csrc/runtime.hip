@@ -58,7 +58,7 @@ struct PinnedPool {
     std::mutex mu;
     std::multimap<uint64_t, void*> free_;   // capacity -> buffer
     uint64_t cached = 0;
-    static constexpr uint64_t kMaxCached = 96ull << 30;
+    static constexpr uint64_t kMaxCached = 64ull << 30;
     void* get(uint64_t cap, uint64_t* got) {
         {
             std::lock_guard<std::mutex> g(mu);
@@ -72,7 +72,16 @@ struct PinnedPool {
             }
         }
         void* p = nullptr;
-        if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) {
+            // pinned memory is limited: give back every cached buffer and retry once
+            {
+                std::lock_guard<std::mutex> g(mu);
+                for (auto& kv : free_) hipHostFree(kv.second);
+                free_.clear();
+                cached = 0;
+            }
+            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) return nullptr;
+        }
         *got = cap;
         return p;
     }
@@ -347,17 +356,18 @@ hipError_t order_after(ckpt_ctx* c, void* stream) {
 }
 
 // Staging geometry. Windows are ranges of whole chunks, floor(slot / C)
-// chunks each, so a window's payload never exceeds its slot. One slot when
-// everything fits in one window; otherwise at least two, so the next
-// window's kernel can run while the previous window is copied out.
+// chunks each, so a window's payload never exceeds its slot. One window
+// when the whole image fits the staging budget (the copy-out then starts
+// after the kernel); otherwise at least two slots, so the next window's
+// kernel runs while the previous window is copied out.
 void pick_staging(const ckpt_ctx* c, const ckpt_opts* o, uint64_t n_chunks, uint32_t C, uint64_t* slot,
                   int* nslots) {
     const uint64_t budget = c->budget;
     const uint64_t all = std::max<uint64_t>(n_chunks, 1) * C;   // one window for every chunk
     if (o && o->window_bytes) {
         *slot = std::max<uint64_t>(o->window_bytes, C);
-    } else if (all <= std::min<uint64_t>(budget, 1ull << 30)) {
-        *slot = all;
+    } else if (all <= budget) {
+        *slot = all;   // the whole image fits the budget: one window
     } else {
         *slot = std::min<uint64_t>(budget / 3, 2ull << 30);
         *slot = std::max<uint64_t>(*slot, std::max<uint64_t>(C, 64ull << 20));
@@ -625,10 +635,22 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     // kinds buffer: zero padding after the kinds (the kinds themselves are written by the kernel)
     HIPCHK(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
 
-    // image buffer
-    ckpt_image* im = image_new(kHeader + tl + upper);
-    if (!im) return CKPT_ENOMEM;
-    uint8_t* himg = im->p;
+    // image buffer: with one window it is allocated once the payload length
+    // is known (a delta's payload is a small part of its upper bound)
+    ckpt_image* im = nullptr;
+    uint8_t* himg = nullptr;
+    if (W > 1) {
+        im = image_new(kHeader + tl + upper);
+        if (!im) return CKPT_ENOMEM;
+        himg = im->p;
+    }
+    auto alloc_image = [&](uint64_t D) -> bool {
+        if (im) return true;
+        im = image_new(kHeader + tl + D);
+        if (!im) return false;
+        himg = im->p;
+        return true;
+    };
     uint64_t* hw = reinterpret_cast<uint64_t*>(c->hsmall);
     uint32_t* crc_dev = reinterpret_cast<uint32_t*>(c->arc.as<uint8_t>() + 32ull * n);
     uint8_t* kind_dev = c->kinds.as<uint8_t>();
@@ -637,8 +659,11 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     auto fail = [&](hipError_t e) {
         hipStreamSynchronize(c->s_main);
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
-        pool().put(im->p, im->cap);
-        delete im;
+        if (im) {
+            pool().put(im->p, im->cap);
+            delete im;
+        }
+        if (e == hipErrorOutOfMemory) return CKPT_ENOMEM;
         if (res) res->hip_error = (int32_t)e;
         return CKPT_EHIP;
     };
@@ -786,6 +811,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         if ((e = hipEventSynchronize(ev[0])) != hipSuccess) return fail(e);
         const uint64_t dw = hw[0];
         if (dw > upper) return fail(hipErrorIllegalState);
+        if (!alloc_image(dw)) return fail(hipErrorOutOfMemory);
         t_link0 = now_ns();
         // the payload in ncs pieces on the side streams
         const uint64_t piece = (std::max<uint64_t>(ceil_div(dw, ncs), 1ull << 20) + 4095) & ~4095ull;
@@ -816,6 +842,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             if (e != hipSuccess) break;
             const uint64_t dw = hw[w];
             if (dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
+            if (!alloc_image(dw)) { e = hipErrorOutOfMemory; break; }
             const int s = (int)(w % nslots);
             hipStream_t cs = c->s_copy[w % ncs];
             if (!t_link0) t_link0 = now_ns();
@@ -850,6 +877,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         if (rc) return fail(hipErrorUnknown);
     }
     const uint64_t D = pos;
+    if (!alloc_image(D)) return fail(hipErrorOutOfMemory);   // a table without chunks
     // tables into the image
     if ((e = hipMemcpyAsync(himg + kHeader, c->arc.p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
         return fail(e);
@@ -1203,9 +1231,11 @@ extern "C" int ckpt_autotune(ckpt_ctx* c, const ckpt_alloc_table* table, uint64_
     static const uint32_t chunks[] = {16384, 65536, 262144};
     static const uint32_t widths[] = {256, 512, 1024};
     static const uint32_t streams[] = {1, 2, 4};
-    double best_rate = -1;
-    ckpt_opts b;
-    memset(&b, 0, sizeof(b));
+    // score: wall time of the trial dump (the host link dominates it); among
+    // trials within 2 % of the fastest, the lowest device time of the chunk
+    // kernels wins
+    struct Trial { ckpt_opts o; double wall, kern; };
+    std::vector<Trial> trials;
     for (uint32_t C : chunks)
         for (uint32_t wt : widths) {
             int T, K;
@@ -1217,8 +1247,8 @@ extern "C" int ckpt_autotune(ckpt_ctx* c, const ckpt_alloc_table* table, uint64_
                 o.chunk_size = C;
                 o.wg_threads = wt;
                 o.copy_streams = ns;
-                o.flags = flags | CKPT_OPT_NO_TIMING;
-                double t_best = 1e30;
+                o.flags = flags & ~CKPT_OPT_NO_TIMING;
+                double t_best = 1e30, k_best = 1e30;
                 for (int rep = 0; rep < 2; ++rep) {
                     ckpt_image* im = nullptr;
                     ckpt_result r;
@@ -1227,16 +1257,23 @@ extern "C" int ckpt_autotune(ckpt_ctx* c, const ckpt_alloc_table* table, uint64_
                     const uint64_t t1 = now_ns();
                     if (rc) return rc;
                     ckpt_image_free(im);
-                    if (rep) t_best = std::min(t_best, (double)(t1 - t0));
+                    if (rep) {
+                        t_best = std::min(t_best, (double)(t1 - t0));
+                        k_best = std::min(k_best, (double)r.ns_kernel);
+                    }
                 }
-                const double rate = taken / t_best;   // bytes per ns = GB/s
-                if (rate > best_rate) {
-                    best_rate = rate;
-                    b = o;
-                    b.flags = flags;
-                }
+                o.flags = flags;
+                trials.push_back({o, t_best, k_best});
             }
         }
+    if (trials.empty()) return CKPT_EINVAL;
+    double wmin = 1e30;
+    for (const Trial& t : trials) wmin = std::min(wmin, t.wall);
+    const Trial* pick = nullptr;
+    for (const Trial& t : trials)
+        if (t.wall <= wmin * 1.02 && (!pick || t.kern < pick->kern)) pick = &t;
+    const ckpt_opts b = pick->o;
+    const double best_rate = taken / pick->wall;   // bytes per ns = GB/s
     {
         std::lock_guard<std::mutex> g(c->mu);
         c->tuned[cls] = std::make_pair(b, best_rate);

@@ -1,0 +1,166 @@
+"""Parity at the benchmark's full sizes and launch configuration.
+
+The oracle cannot re-dump tens of GB quickly, so these tests check what it
+can compute one by one -- CRC-32C and kind of sampled chunks, the payload
+record of sampled chunks, the table digests -- plus properties that hold at
+any size (header fields, payload length, the restored bytes equal to the
+dumped ones, in full). Each test names its workload and seed."""
+import os
+import struct
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as corc  # noqa: E402
+from paper_2502_16631_amd import mickpt as mk  # noqa: E402
+import workloads  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+C = 65536
+ZERO, DATA, UNCHANGED = 0, 1, 2
+
+
+def _bytes_of(t):
+    return t.reshape(-1).view(torch.uint8) if t.numel() else torch.zeros(0, dtype=torch.uint8, device=t.device)
+
+
+def _check_image(img, table, samples=1500, seed=0, prev_table=None):
+    v = img.view()
+    (magic, ver, flags, c, n, nc, D, base, res, N, tcrc, hcrc) = struct.unpack_from("<8sIIIIQQIIQII", v[:64].tobytes())
+    sizes = [t.numel() * t.element_size() for _, t in table]
+    assert magic == b"MICKPT01" and c == C and n == len(table) and N == sum(sizes)
+    assert nc == sum((s + C - 1) // C for s in sizes)
+    tl = (32 * n + 5 * nc + 15) & ~15
+    assert v.size == 64 + tl + D
+    assert corc.crc32c(v[:60]) == hcrc and corc.crc32c(v[64:64 + tl]) == tcrc
+    recs = np.frombuffer(v[64:64 + 32 * n].tobytes(), dtype=np.uint64).reshape(n, 4)
+    crcs = np.frombuffer(v[64 + 32 * n:64 + 32 * n + 4 * nc].tobytes(), dtype=np.uint32)
+    kinds = v[64 + 32 * n + 4 * nc:64 + 32 * n + 5 * nc]
+    first = np.concatenate([[0], np.cumsum([(s + C - 1) // C for s in sizes])[:-1]]).astype(np.int64)
+    assert np.array_equal(recs[:, 1], np.array(sizes, dtype=np.uint64))
+    assert np.array_equal(recs[:, 2], first.astype(np.uint64))
+    # payload offsets from the kinds (a property of the format)
+    lens = np.full(nc, C, dtype=np.int64)
+    for a, s in enumerate(sizes):
+        nk = (s + C - 1) // C
+        if nk:
+            lens[first[a] + nk - 1] = s - (nk - 1) * C
+    plen = np.where(kinds == DATA, (lens + 15) & ~15, 0)
+    off = np.concatenate([[0], np.cumsum(plen)[:-1]])
+    assert int(plen.sum()) == D
+    # sampled chunks: CRC-32C and kind from the oracle, payload bytes
+    rng = np.random.default_rng(seed)
+    alloc_of = np.searchsorted(first, np.arange(nc), side="right") - 1
+    pick = rng.choice(nc, size=min(samples, nc), replace=False)
+    pick = np.union1d(pick, [0, nc - 1])
+    for g in pick:
+        a = int(alloc_of[g])
+        k = int(g - first[a])
+        buf = _bytes_of(table[a][1])
+        chunk = buf[k * C:k * C + int(lens[g])].cpu().numpy()
+        assert corc.crc32c(chunk) == int(crcs[g]), g
+        if not chunk.any():
+            want = ZERO
+        elif prev_table is not None and int(crcs[g]) == corc.crc32c(
+                _bytes_of(prev_table[a][1])[k * C:k * C + int(lens[g])].cpu().numpy()):
+            want = UNCHANGED
+        else:
+            want = DATA
+        assert int(kinds[g]) == want, g
+        if want == DATA:
+            rec = v[64 + tl + int(off[g]):64 + tl + int(off[g]) + int(plen[g])]
+            assert np.array_equal(rec[:int(lens[g])], chunk) and not rec[int(lens[g]):].any()
+    # whole-allocation CRCs of the smaller allocations
+    small = [a for a, s in enumerate(sizes) if s <= (64 << 20)][:20]
+    for a in small:
+        assert corc.crc32c(_bytes_of(table[a][1]).cpu().numpy()) == int(recs[a, 3] & 0xFFFFFFFF)
+    return D, kinds
+
+
+def _restore_equal(ctx, img, table, opts):
+    targets = [(i, torch.empty_like(t)) for i, t in table]
+    rc, res = mk.ckpt_restore(ctx, img, targets, opts=opts)
+    assert rc == 0, (mk.ckpt_strerror(rc), res.first_bad_chunk)
+    torch.cuda.synchronize()
+    for (_, a), (_, b) in zip(table, targets):
+        assert torch.equal(_bytes_of(a), _bytes_of(b))
+
+
+@pytest.mark.timeout(600)
+def test_training_state_full_size():
+    """decoder-1.3B training state, seed 2, 303 allocations, ~27 GB; the bench's
+    configuration: one staging window, 64 KiB chunks."""
+    table = workloads.training_state("cuda", seed=2)
+    torch.cuda.synchronize()
+    N = sum(t.numel() * t.element_size() for _, t in table)
+    ctx = mk.ckpt_ctx_create(0, 64 << 30)
+    try:
+        opts = mk.make_opts(chunk_size=C)
+        rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+        assert rc == 0 and res.windows == 1
+        D, kinds = _check_image(img, table, seed=2)
+        assert (kinds == DATA).all() and D >= N     # random-valued state: every chunk is DATA
+        _restore_equal(ctx, img, table, opts)
+        img.free()
+    finally:
+        mk.ckpt_ctx_destroy(ctx)
+
+
+@pytest.mark.timeout(600)
+def test_hpc_incremental_full_size():
+    """HPC image, seed 3, 512 allocations, 40 GB, ~60 % zero chunks; 5 % of the
+    chunks rewritten (seed 33); delta dump, then base restore + delta apply."""
+    table, _ = workloads.hpc_state("cuda", seed=3)
+    torch.cuda.synchronize()
+    ctx = mk.ckpt_ctx_create(0, 64 << 30)
+    try:
+        opts = mk.make_opts(chunk_size=C)
+        rc, base, _ = mk.ckpt_dump(ctx, table, opts=opts)
+        assert rc == 0
+        prev = [(i, t.clone()) for i, t in table]
+        workloads.mutate_runs(table, seed=33, chunk=C, frac=0.05, run_mean=16)
+        rc, delta, dres = mk.ckpt_dump(ctx, table, prev=base, opts=opts)
+        assert rc == 0 and dres.n_unchanged > 0
+        _check_image(delta, table, samples=1500, seed=3, prev_table=prev)
+        del prev
+        # base then delta, in place: equals the new state
+        new = [(i, t.clone()) for i, t in table]
+        rc, _ = mk.ckpt_restore(ctx, base, table, opts=opts)
+        assert rc == 0
+        rc, r = mk.ckpt_restore(ctx, delta, table, opts=opts)
+        assert rc == 0, (mk.ckpt_strerror(rc), r.first_bad_chunk)
+        torch.cuda.synchronize()
+        for (_, a), (_, b) in zip(new, table):
+            assert torch.equal(a, b)
+    finally:
+        mk.ckpt_ctx_destroy(ctx)
+
+
+@pytest.mark.timeout(900)
+def test_fragmented_batched_full_size():
+    """10,000 allocations, seed 4, 60 GB, 256 KiB-aligned zero blocks; graph
+    form (one launch) and per-allocation launches give the same image."""
+    table = workloads.fragmented_state("cuda", seed=4)
+    torch.cuda.synchronize()
+    ctx = mk.ckpt_ctx_create(0, 96 << 30)
+    try:
+        opts = mk.make_opts(chunk_size=C, flags=mk.OPT_GRAPH)
+        rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+        assert rc == 0, (mk.ckpt_strerror(rc), res.hip_error)
+        assert res.windows == 1
+        _check_image(img, table, seed=4)
+        rc, img2, res2 = mk.ckpt_dump(ctx, table, opts=mk.make_opts(chunk_size=C, flags=mk.OPT_PER_ALLOC))
+        assert rc == 0, (mk.ckpt_strerror(rc), res2.hip_error)
+        assert res2.windows >= len([t for _, t in table if t.numel()])
+        assert np.array_equal(img.view(), img2.view())
+        img2.free()
+        _restore_equal(ctx, img, table, opts)
+        img.free()
+    finally:
+        mk.ckpt_ctx_destroy(ctx)
