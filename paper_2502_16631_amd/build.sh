@@ -8,7 +8,10 @@ BUILD="$HERE/_build"
 mkdir -p "$BUILD"
 FLAGS=(--offload-arch=gfx950 -O3 -std=c++17 -fPIC -Wall -Wno-unused-result -Wno-unused-value -Wno-pass-failed
        -Xclang -target-feature -Xclang -packed-fp32-ops)
-hipcc "${FLAGS[@]}" -c "$SRC/kernels.hip" -o "$BUILD/kernels.o" &
+# Every atomic in the kernels is issued by one lane; without the atomic
+# optimizer the ticket fetch does not wait for its result where it is issued.
+KFLAGS=(-mllvm -amdgpu-atomic-optimizer-strategy=None)
+hipcc "${FLAGS[@]}" "${KFLAGS[@]}" -c "$SRC/kernels.hip" -o "$BUILD/kernels.o" &
 p1=$!
 hipcc "${FLAGS[@]}" -c "$SRC/runtime.hip" -o "$BUILD/runtime.o" &
 p2=$!

@@ -71,15 +71,18 @@ static_assert(sizeof(AllocDesc) == 64, "descriptor layout");
 
 // Engine constants for one (work-group width T, chunk size C) pair. The
 // chunk kernels copy the tables into LDS once per persistent work-group.
-//   dt[j][x]  = r(byte x followed by 15-j zero bytes): the 16-byte block
-//               digest is the xor of dt[j][byte j] over its 16 bytes;
-//   jt[i][x]  = ((x << 8i)) * x^(8R), R = 16 T: advances a lane's running
-//               digest over one row of the tile;
-//   lane[t]   = x^(8 * 16 (T-1-t)): aligns lane t's interleaved stream to
-//               the end of the chunk.
+//   dt[j][x]  = r(byte x followed by 15-j zero bytes) * x^(8G), G = 16 (T-1):
+//               the digest of a 16-byte block followed by the G bytes that
+//               separate it from the lane's next block (the other lanes'
+//               share of the row, read as zeros) is the xor of dt[j][byte j]
+//               over its 16 bytes. A lane's running digest is folded into
+//               the first four bytes of its next block before the lookups
+//               (r(M || B) = r((r(M) as 4 bytes xor B[0..3]) || B[4..15]), so
+//               no separate step advances it over a row;
+//   lane[t]   = x^(-8 * 16 t): lane t's stream then ends G bytes past the
+//               end of the tile; this moves it back to its own position.
 struct EngineConsts {
     uint32_t dt[16 * 256];
-    uint32_t jt[4 * 256];
     uint32_t lane[1024];
     uint32_t full_init;    // (~0) * x^(8C)
     uint32_t full_x;       // x^(8C)

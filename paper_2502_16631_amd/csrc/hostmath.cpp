@@ -80,19 +80,18 @@ uint32_t crc_combine(uint32_t crc_a, uint32_t crc_b, uint64_t len_b) {
 
 void build_engine_consts(EngineConsts* ec, int T, uint32_t C) {
     memset(ec, 0, sizeof(*ec));
-    // raw CRC of one byte followed by (15 - j) zero bytes
+    // raw CRC of one byte followed by (15 - j) zero bytes and by the gap of
+    // 16 (T - 1) bytes to the lane's next block
+    const uint32_t gap = xpow8(16ull * (uint64_t)(T - 1));
     for (uint32_t x = 0; x < 256; ++x) {
         uint32_t r = x;
         for (int i = 0; i < 8; ++i) r = gf_xtimes(r);   // r(x) = x * x^8 ... in register form
         for (int j = 15; j >= 0; --j) {
-            ec->dt[j * 256 + x] = r;
+            ec->dt[j * 256 + x] = gf_mul(r, gap);
             r = gf_mul(r, xpow8(1));
         }
     }
-    const uint32_t row = xpow8(16ull * (uint64_t)T);   // x^(8R), R = 16T
-    for (int i = 0; i < 4; ++i)
-        for (uint32_t x = 0; x < 256; ++x) ec->jt[i * 256 + x] = gf_mul(x << (8 * i), row);
-    for (int t = 0; t < 1024; ++t) ec->lane[t] = t < T ? xpow8(16ull * (uint64_t)(T - 1 - t)) : 0u;
+    for (int t = 0; t < 1024; ++t) ec->lane[t] = t < T ? xinvpow8(16ull * (uint64_t)t) : 0u;
     ec->full_x = xpow8(C);
     ec->full_init = gf_mul(0xFFFFFFFFu, ec->full_x);
     uint32_t p = kX1;

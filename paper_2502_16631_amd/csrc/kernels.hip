@@ -10,11 +10,12 @@
 // row r, so every row is one fully coalesced 128-bit load per thread. The
 // CRC-32C of the chunk is computed without moving the data between lanes:
 // lane t keeps the raw CRC of its own interleaved stream (its blocks, with
-// the other lanes' bytes read as zeros). Per row the running value is
-// advanced over the 16T bytes of the row with four lookups (jt) and the
-// block's 16 bytes are folded in with sixteen lookups (dt); both tables
-// live in LDS. At the end lane t's value is shifted to the end of the chunk
-// (multiplied by x^(8*16(T-1-t))) and the lanes' values are xor-reduced.
+// the other lanes' bytes read as zeros). Per row the running value is xored
+// into the first four bytes of the lane's block and the block is reduced
+// with sixteen lookups in tables (dt, in LDS) that also carry the shift over
+// the rest of the row, so advancing over a row costs no extra lookup. At the
+// end lane t's value is moved to its place in the chunk (multiplied by
+// x^(-8*16t)) and the lanes' values are xor-reduced.
 // Modes:
 //   dump    - digest + zero test + unchanged test against the previous
 //             digest table, then the chunk's payload offset from a decoupled
@@ -56,18 +57,20 @@ __device__ inline uint32_t wave_xor(uint32_t v) {
     return v;
 }
 
-// Decoupled look-back (single-pass prefix scan): the calling wave publishes
-// its aggregate `agg` at position idx, sums the aggregates of its
-// predecessors back to the nearest published inclusive prefix, publishes its
-// own inclusive prefix and returns the exclusive one. All 64 lanes call it.
-__device__ uint64_t lookback(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch, uint32_t* err) {
+// Decoupled look-back (single-pass prefix scan). lb_publish stores the
+// aggregate `agg` of position idx (at position 0 it is the inclusive
+// prefix); lb_walk then sums the aggregates of the predecessors back to the
+// nearest published inclusive prefix, publishes the inclusive prefix of idx
+// and returns the exclusive one (all 64 lanes of one wave call it).
+__device__ inline void lb_publish(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch) {
+    const uint64_t tag = (uint64_t)(epoch & kEpochMask) << 40;
+    st_relaxed(&status[idx], (idx == 0 ? kStInc : kStAgg) | tag | agg);
+}
+
+__device__ uint64_t lb_walk(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch, uint32_t* err) {
     const int lane = threadIdx.x & 63;
     const uint64_t tag = (uint64_t)(epoch & kEpochMask) << 40;
-    if (idx == 0) {
-        if (lane == 0) st_relaxed(&status[0], kStInc | tag | agg);
-        return 0;
-    }
-    if (lane == 0) st_relaxed(&status[idx], kStAgg | tag | agg);
+    if (idx == 0) return 0;
     uint64_t excl = 0;
     int64_t base = (int64_t)idx - 1;
     for (;;) {
@@ -101,13 +104,18 @@ __device__ uint64_t lookback(uint64_t* status, uint64_t idx, uint64_t agg, uint3
     return excl;
 }
 
+__device__ inline uint64_t lookback(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch, uint32_t* err) {
+    if ((threadIdx.x & 63) == 0) lb_publish(status, idx, agg, epoch);
+    return lb_walk(status, idx, agg, epoch, err);
+}
+
 // last allocation whose first chunk is <= g (empty allocations share their
 // successor's first chunk and are therefore never selected)
 __device__ inline uint32_t find_alloc(const AllocDesc* a, uint32_t n, uint64_t g) {
     uint32_t lo = 0, hi = n;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid].first <= g) lo = mid; else hi = mid;
+        if (*(const __attribute__((address_space(4))) uint64_t*)(&a[mid].first) <= g) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -165,17 +173,13 @@ __device__ inline uint32_t blk16(v4u v, const uint32_t* dt) {
            dt[14 * 256 + ((v.w >> 16) & 255)] ^ dt[15 * 256 + (v.w >> 24)];
 }
 
-__device__ inline uint32_t jump(uint32_t acc, const uint32_t* jt) {
-    return jt[acc & 255] ^ jt[256 + ((acc >> 8) & 255)] ^ jt[512 + ((acc >> 16) & 255)] ^ jt[768 + (acc >> 24)];
-}
-
 template <int K>
-__device__ inline uint32_t crc_rows(const v4u (&v)[K], uint32_t acc, bool cont, const uint32_t* dt,
-                                    const uint32_t* jt) {
+__device__ inline uint32_t crc_rows(const v4u (&v)[K], uint32_t acc, const uint32_t* dt) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        if (r > 0 || cont) acc = jump(acc, jt);
-        acc ^= blk16(v[r], dt);
+        v4u b = v[r];
+        b.x ^= acc;
+        acc = blk16(b, dt);
         // one row of lookups in flight at a time: keeps the register
         // footprint near the data itself (other waves hide the latency)
         __builtin_amdgcn_sched_barrier(0);
@@ -249,6 +253,39 @@ __device__ inline void store_rows_padded(const v4u (&v)[K], uint8_t* base, uint6
     }
 }
 
+// Work-group barrier for LDS traffic only. __syncthreads also waits for
+// every outstanding global load and store of the wave (its release fence);
+// this one lets them run on, which keeps streamed rows in flight across it.
+// Only LDS data is exchanged between the waves of a work-group across it.
+__device__ inline void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Is p true in any thread of the work-group? (s_any: one word per wave)
+template <int NW>
+__device__ inline uint32_t wg_any_lds(bool p, uint32_t* s_any) {
+    const uint64_t b = __ballot(p);
+    if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = b != 0;
+    lds_barrier();
+    uint32_t r = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) r |= s_any[w];
+    return r;
+}
+
+template <int NW>
+__device__ inline uint32_t wg_xor_lds(uint32_t x, uint32_t* s_red) {
+    x = wave_xor(x);
+    if constexpr (NW > 1) {
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = x;
+        lds_barrier();
+        x = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) x ^= s_red[w];
+    }
+    return x;
+}
+
 template <int NW>
 __device__ inline uint32_t wg_xor(uint32_t x, uint32_t* s_red) {
     x = wave_xor(x);
@@ -271,8 +308,8 @@ k_chunks(JobList jl) {
     constexpr int NW = NT / 64;
     constexpr uint32_t TILE = 16u * T * K;
     __shared__ uint32_t s_dt[16 * 256];
-    __shared__ uint32_t s_jt[4 * 256];
     __shared__ uint32_t s_red[NW];
+    __shared__ uint32_t s_any[NW];
     __shared__ uint32_t s_tk[2];
     __shared__ uint64_t s_off;
 
@@ -280,7 +317,6 @@ k_chunks(JobList jl) {
     const bool active = T >= 64 || tid < T;
     const EngineConsts* ec = jl.job[0].ec;
     for (int i = tid; i < 16 * 256; i += NT) s_dt[i] = ec->dt[i];
-    for (int i = tid; i < 4 * 256; i += NT) s_jt[i] = ec->jt[i];
     const uint32_t lanec = active ? ec->lane[tid] : 0u;
     const uint32_t full_init = ec->full_init;
     const uint32_t C = jl.job[0].C;
@@ -295,8 +331,8 @@ k_chunks(JobList jl) {
     // one are held by running work-groups, so every look-back wait ends.
     if (tid == 0) s_tk[0] = atomicAdd(jl.ticket, 1u);
     for (uint32_t it = 0;; ++it) {
-        __syncthreads();
-        const uint64_t tk = (uint64_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
+        lds_barrier();
+        const uint64_t tk = (uint32_t)__builtin_amdgcn_readfirstlane(s_tk[it & 1]);
         if (tk >= total) break;
         if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(jl.ticket, 1u);
         uint32_t jj = 0;
@@ -347,10 +383,10 @@ k_chunks(JobList jl) {
                 const uint64_t rem = len > lp ? len - lp : 0;
                 load_rows_staged<T, K>(v, src + lp, rem, ltid, active, &padbad);
                 if (rem) store_rows_exact<T, K>(v, aptr + lp, rem, ltid, active);
-                acc = crc_rows<K>(v, acc, p > 0, s_dt, s_jt);
+                acc = crc_rows<K>(v, acc, s_dt);
             }
-            uint32_t raw = wg_xor<NW>(gf_mul(acc, lc), s_red);
-            const int pb = __syncthreads_or(padbad != 0);
+            uint32_t raw = wg_xor_lds<NW>(gf_mul(acc, lc), s_red);
+            const uint32_t pb = wg_any_lds<NW>(padbad != 0, s_any);
             if (!full) raw = gf_mul(raw, ad.tail_unshift);
             const uint32_t crc = ~(raw ^ init);
             if (tid == 0 && (crc != job.ref_crc[g] || pb)) atomicMin(job.bad, (unsigned long long)g);
@@ -359,16 +395,23 @@ k_chunks(JobList jl) {
             v4u v[K];
             uint32_t acc = 0, orw = 0;
             int any;
+            // Without a previous digest for the allocation the kind, and so
+            // the payload length, follows from the zero test alone: the
+            // aggregate is then published before the digest is computed, so
+            // the successors' look-backs rarely wait on this chunk.
+            const uint64_t len16 = (len + 15u) & ~15u;
+            const bool early = MODE == kModeDump && (job.prev_crc == nullptr || ad.prev_first == ~0ull);
             if (P == 1) {
                 load_rows<T, K>(v, aptr, len, ltid, active);
                 if constexpr (MODE == kModeDump) {
 #pragma unroll
                     for (int r = 0; r < K; ++r) orw |= or4(v[r]);
-                    any = __syncthreads_or(orw != 0);
-                    if (any) acc = crc_rows<K>(v, 0, false, s_dt, s_jt);
+                    any = wg_any_lds<NW>(orw != 0, s_any);
+                    if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
+                    if (any) acc = crc_rows<K>(v, 0, s_dt);
                 } else {
                     any = 1;
-                    acc = crc_rows<K>(v, 0, false, s_dt, s_jt);
+                    acc = crc_rows<K>(v, 0, s_dt);
                 }
             } else {
                 for (uint32_t p = 0; p < P; ++p) {
@@ -376,13 +419,14 @@ k_chunks(JobList jl) {
                     load_rows<T, K>(v, aptr + lp, len > lp ? len - lp : 0, ltid, active);
 #pragma unroll
                     for (int r = 0; r < K; ++r) orw |= or4(v[r]);
-                    acc = crc_rows<K>(v, acc, p > 0, s_dt, s_jt);
+                    acc = crc_rows<K>(v, acc, s_dt);
                 }
-                any = (MODE == kModeDump) ? __syncthreads_or(orw != 0) : 1;
+                any = (MODE == kModeDump) ? wg_any_lds<NW>(orw != 0, s_any) : 1;
+                if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
             }
             uint32_t crc = ~init;
             if (any) {
-                uint32_t raw = wg_xor<NW>(gf_mul(acc, lc), s_red);
+                uint32_t raw = wg_xor_lds<NW>(gf_mul(acc, lc), s_red);
                 if (!full) raw = gf_mul(raw, ad.tail_unshift);
                 crc = ~(raw ^ init);
             }
@@ -403,13 +447,13 @@ k_chunks(JobList jl) {
                     job.crc_out[g] = crc;
                     job.kind_out[g] = kd;
                 }
-                const uint64_t len16 = (len + 15u) & ~15u;
                 const uint64_t plen = kd == kData ? len16 : 0;
                 if (tid < 64) {
-                    const uint64_t e = lookback(job.status, g - job.g0, plen, job.epoch, job.err);
+                    const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
+                                             : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
                     if (tid == 0) s_off = e;
                 }
-                __syncthreads();
+                lds_barrier();
                 const uint64_t excl = s_off;
                 if (kd == kData) {
                     uint8_t* dst = job.slot + excl;
@@ -427,6 +471,194 @@ k_chunks(JobList jl) {
                 if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
             }
         }
+    }
+}
+
+// Loads through the scalar cache, for tables that no work-group writes
+// while the kernel runs (descriptors, the chunk map, the previous digest
+// table); the dispatch invalidates the scalar cache, so what earlier
+// kernels wrote is seen. They stay off the vector memory counter, so
+// waiting for them never waits for the streamed rows.
+template <typename V>
+__device__ inline V ld_const(const V* p) {
+    return *(const __attribute__((address_space(4))) V*)(p);
+}
+
+// Where the ticket tk falls: its job, global chunk, allocation and chunk
+// geometry. Every value is uniform across the work-group.
+struct ChunkAt {
+    uint32_t jj;            // job
+    uint32_t len;           // valid bytes
+    uint64_t g;             // global chunk of the job
+    uint64_t k;             // chunk within its allocation
+    uint64_t prev_first;    // first chunk of the allocation in the previous table, or ~0
+    uint32_t tail_init;
+    uint32_t tail_unshift;
+    const uint8_t* ptr;     // first byte of the chunk
+};
+
+template <uint32_t C>
+__device__ inline ChunkAt chunk_at(const JobList& jl, uint64_t tk) {
+    ChunkAt c;
+    uint32_t jj = 0;
+    while (jj + 1 < jl.n_jobs && jl.prefix[jj + 1] <= tk) ++jj;
+    const ChunkJob& job = jl.job[jj];
+    c.jj = jj;
+    c.g = job.g0 + (tk - jl.prefix[jj]);
+    const uint32_t a = job.amap ? ld_const(job.amap + c.g) : find_alloc(job.allocs, job.n_allocs, c.g);
+    const AllocDesc* ad = job.allocs + a;
+    const uint64_t first = ld_const(&ad->first), size = ld_const(&ad->size);
+    c.k = c.g - first;
+    const uint64_t nk = (size + C - 1) / C;
+    c.len = (c.k + 1 == nk) ? ld_const(&ad->tail_len) : C;
+    c.prev_first = ld_const(&ad->prev_first);
+    c.tail_init = ld_const(&ad->tail_init);
+    c.tail_unshift = ld_const(&ad->tail_unshift);
+    c.ptr = reinterpret_cast<const uint8_t*>(ld_const(&ad->ptr)) + c.k * C;
+    return c;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+// Dump mode for chunks of exactly one tile (C = 16 T K), streamed: while a
+// work-group digests, scans and stores its current chunk from registers,
+// the rows of its next chunk are already on their way -- the first K-1
+// rows straight into LDS (global_load_lds_dwordx4: lane i of a wave lands
+// at the wave's LDS base + 16 i, so every lane later reads back exactly the
+// 16 bytes it requested and no barrier is needed between the waves), the
+// last row into registers. HBM reads therefore stay in flight during the
+// work-group's LDS lookups, barriers and look-back. In the last, partial
+// chunk of an allocation only whole 16-byte blocks below its end are
+// streamed; the block that straddles the end is read byte by byte and the
+// blocks past it are zeros. Tickets: a work-group holds its current ticket,
+// the next one (being streamed) and the one after (a value only); every
+// ticket below its current one is held by a running work-group, so
+// look-back waits end.
+template <int T, int K>
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4)))
+k_dump_stream(JobList jl) {
+    static_assert(T >= 64 && T % 64 == 0, "whole waves");
+    constexpr int NW = T / 64;
+    constexpr uint32_t R = 16u * T;       // bytes per row
+    constexpr uint32_t C = R * K;         // the chunk is one tile
+    constexpr uint32_t BUF = K > 1 ? (K - 1) * R : 16;
+    __shared__ uint32_t s_dt[16 * 256];
+    __shared__ __attribute__((aligned(16))) uint8_t s_buf[BUF];
+    __shared__ uint32_t s_red[NW];
+    __shared__ uint32_t s_any[NW];
+    __shared__ uint32_t s_tk[2];
+    __shared__ uint64_t s_off;
+
+    const int tid = threadIdx.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+    const EngineConsts* ec = jl.job[0].ec;
+    for (int i = tid; i < 16 * 256; i += T) s_dt[i] = ec->dt[i];
+    const uint32_t lanec = ec->lane[tid];
+    const uint32_t full_init = ec->full_init;
+    const uint64_t total = jl.prefix[jl.n_jobs];
+    if (tid == 0) {
+        s_tk[0] = atomicAdd(jl.ticket, 1u);
+        s_tk[1] = atomicAdd(jl.ticket, 1u);
+    }
+    __syncthreads();
+
+    // start the whole 16-byte blocks of a chunk on their way (K-1 rows to
+    // LDS, the last row to registers)
+    auto stream = [&](const ChunkAt& c, v4u& last) {
+        // this wave's reads of the buffer must be complete before it is refilled
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int r = 0; r < K - 1; ++r)
+            if (r * R + 16u * tid + 16u <= c.len)
+                __builtin_amdgcn_global_load_lds((glb_void*)(c.ptr + r * R + 16u * tid),
+                                                 (lds_void*)(s_buf + r * R + wave * 1024u), 16, 0, 0);
+        const uint32_t o = (K - 1) * R + 16u * tid;
+        last = o + 16u <= c.len ? gload(c.ptr + o) : vzero();
+    };
+
+    uint64_t tk = (uint32_t)__builtin_amdgcn_readfirstlane(s_tk[0]);
+    ChunkAt cur{};
+    v4u last = vzero();
+    if (tk < total) {
+        cur = chunk_at<C>(jl, tk);
+        stream(cur, last);
+    }
+    for (uint32_t it = 0;; ++it) {
+        if (tk >= total) break;
+        // the current chunk into registers (its streamed blocks have landed
+        // once the vector memory counter drains)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        v4u v[K];
+        uint32_t orw = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const uint32_t o = r * R + 16u * tid;
+            v4u x = r < K - 1 ? *reinterpret_cast<const v4u*>(s_buf + r * R + 16u * tid) : last;
+            if (o + 16u > cur.len) x = o < cur.len ? load_partial(cur.ptr + o, cur.len - o) : vzero();
+            v[r] = x;
+            orw |= or4(x);
+        }
+        // the ticket after next; its value is needed only at the end of the
+        // iteration
+        uint32_t tk2 = 0;
+        if (tid == 0) tk2 = atomicAdd(jl.ticket, 1u);
+        const uint64_t tk_next = (uint32_t)__builtin_amdgcn_readfirstlane(s_tk[(it + 1) & 1]);
+
+        const ChunkJob& job = jl.job[cur.jj];
+        const uint64_t g = cur.g;
+        const uint32_t len = cur.len;
+        const bool full = len == C;
+        const uint32_t init = full ? full_init : cur.tail_init;
+        const uint64_t len16 = (len + 15u) & ~15u;
+        uint32_t lc = lanec;
+        uint32_t ltid = (uint32_t)tid;
+        asm volatile("" : "+v"(lc), "+v"(ltid));
+
+        // (LDS-only barriers from here on: streamed blocks stay in flight)
+        const uint32_t any = wg_any_lds<NW>(orw != 0, s_any);
+        // Without a previous digest for the allocation the payload length
+        // follows from the zero test: the look-back runs now, before the
+        // digest, so the chunk's inclusive prefix is published early and the
+        // successors' look-backs stop right behind them. (Wave 0 issues its
+        // share of the next chunk's loads after the look-back: the status
+        // loads would otherwise wait for them on the vector memory counter.)
+        const bool early = job.prev_crc == nullptr || cur.prev_first == ~0ull;
+        if (early && tid < 64) {
+            const uint64_t e = lookback(job.status, g - job.g0, any ? len16 : 0, job.epoch, job.err);
+            if (tid == 0) s_off = e;
+        }
+        ChunkAt nxt{};
+        if (tk_next < total) {
+            nxt = chunk_at<C>(jl, tk_next);
+            stream(nxt, last);
+        }
+        uint32_t acc = 0;
+        if (any) acc = crc_rows<K>(v, 0, s_dt);
+        if (tid == 0) s_tk[it & 1] = tk2;
+        uint32_t raw = wg_xor_lds<NW>(gf_mul(acc, lc), s_red);
+        if (!full) raw = gf_mul(raw, cur.tail_unshift);
+        const uint32_t crc = ~(raw ^ init);
+        uint8_t kd = kData;
+        if (!any) kd = kZero;
+        else if (!early && ld_const(job.prev_crc + cur.prev_first + cur.k) == crc) kd = kUnchanged;
+        if (tid == 0) {
+            job.crc_out[g] = crc;
+            job.kind_out[g] = kd;
+        }
+        const uint64_t plen = kd == kData ? len16 : 0;
+        if (!early) {
+            if (tid < 64) {
+                const uint64_t e = lookback(job.status, g - job.g0, plen, job.epoch, job.err);
+                if (tid == 0) s_off = e;
+            }
+            lds_barrier();
+        }
+        const uint64_t excl = s_off;
+        if (kd == kData) store_rows_padded<T, K>(v, job.slot + excl, len16, ltid, true);
+        if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
+        tk = tk_next;
+        cur = nxt;
     }
 }
 
@@ -571,7 +803,15 @@ template <int T, int K>
 hipError_t launch_tk(int mode, const JobList& jl, int grid, hipStream_t s) {
     constexpr int NT = T < 64 ? 64 : T;
     switch (mode) {
-        case kModeDump: hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, jl); break;
+        case kModeDump:
+            if constexpr (T >= 64) {
+                if (jl.job[0].C == 16u * T * K) {
+                    hipLaunchKernelGGL((k_dump_stream<T, K>), dim3(grid), dim3(T), 0, s, jl);
+                    break;
+                }
+            }
+            hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, jl);
+            break;
         case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, jl); break;
@@ -584,7 +824,17 @@ template <int T, int K>
 hipError_t occ_tk(int mode, int* n) {
     constexpr int NT = T < 64 ? 64 : T;
     switch (mode) {
-        case kModeDump: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDump>, NT, 0);
+        case kModeDump: {
+            // the smaller of the two dump kernels' residencies (which one
+            // runs depends on the chunk size)
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDump>, NT, 0);
+            if constexpr (T >= 64) {
+                int m = 0;
+                if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_dump_stream<T, K>, T, 0);
+                if (e == hipSuccess && m < *n) *n = m;
+            }
+            return e;
+        }
         case kModeDigest: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDigest>, NT, 0);
         case kModeVerify: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeVerify>, NT, 0);
         case kModeRestore: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeRestore>, NT, 0);

@@ -961,13 +961,10 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     }
     // descriptors from the image's records (sizes, grid) and the caller's pointers
     std::vector<AllocDesc> d(v.n_allocs);
-    uint64_t upper = 0;
     for (uint64_t a = 0; a < v.n_allocs; ++a) {
         const uint8_t* r = v.recs + 32 * a;
         const void* ptr = a < n ? table->v[a].dev_ptr : nullptr;
         make_desc(&d[a], get64(r), ptr, get64(r + 8), get64(r + 16), kNoChunk, C);
-        const uint64_t nk = ceil_div(d[a].size, C);
-        if (nk) upper += (nk - 1) * C + round16(d[a].tail_len);
     }
     const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
     int T, K;

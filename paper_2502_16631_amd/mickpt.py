@@ -132,11 +132,27 @@ def lib():
     return _lib
 
 
+class _Bytes:
+    """Array-interface holder for image bytes; keeps the Image alive while a
+    numpy view of it exists."""
+
+    def __init__(self, owner, addr, n):
+        self._owner = owner
+        self.__array_interface__ = {"shape": (n,), "typestr": "|u1", "data": (addr, False), "version": 3}
+
+
 class Image:
-    """An image owned by the library (pinned host memory)."""
+    """An image owned by the library (pinned host memory); released by free()
+    or when the last reference (including numpy views) goes away."""
 
     def __init__(self, handle):
         self.handle = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
     def nbytes(self):
         p, n = ctypes.c_void_p(), _u64()
@@ -152,8 +168,7 @@ class Image:
             raise RuntimeError(ckpt_strerror(rc))
         if n.value == 0:
             return np.zeros(0, np.uint8)
-        buf = (ctypes.c_uint8 * n.value).from_address(p.value)
-        return np.frombuffer(buf, dtype=np.uint8)
+        return np.asarray(_Bytes(self, p.value, n.value))
 
     def tobytes(self):
         return self.view().tobytes()

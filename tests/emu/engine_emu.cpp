@@ -1,6 +1,7 @@
 // CPU emulation of the GPU chunk engine's CRC decomposition, for testing
 // the engine constants on a machine without a GPU. It reproduces the
-// per-lane interleaved streams, the row jump, the lane alignment, the tail
+// per-lane interleaved streams, the fold of the running digest into the
+// next block, the lane alignment, the tail
 // correction and the per-allocation combine exactly as the kernels do, using
 // the library's own constant builder; the tests compare its results with
 // the SSE4.2 hardware CRC-32C.
@@ -17,10 +18,6 @@ static uint32_t blk16(const uint8_t* b, const EngineConsts& ec) {
     for (int j = 0; j < 16; ++j) h ^= ec.dt[j * 256 + b[j]];
     return h;
 }
-static uint32_t jump(uint32_t acc, const EngineConsts& ec) {
-    return ec.jt[acc & 255] ^ ec.jt[256 + ((acc >> 8) & 255)] ^ ec.jt[512 + ((acc >> 16) & 255)] ^
-           ec.jt[768 + (acc >> 24)];
-}
 
 extern "C" uint32_t emu_chunk_crc(const uint8_t* p, uint32_t len, uint32_t C, int T, int K) {
     static EngineConsts ec;
@@ -31,11 +28,11 @@ extern "C" uint32_t emu_chunk_crc(const uint8_t* p, uint32_t len, uint32_t C, in
         uint32_t acc = 0;
         for (uint32_t pp = 0; pp < P; ++pp)
             for (int r = 0; r < K; ++r) {
-                if (pp || r) acc = jump(acc, ec);
                 uint8_t blk[16];
                 const uint32_t o = pp * TILE + r * R + 16u * t;
                 for (int j = 0; j < 16; ++j) blk[j] = (o + j < len) ? p[o + j] : 0;
-                acc ^= blk16(blk, ec);
+                for (int j = 0; j < 4; ++j) blk[j] ^= (uint8_t)(acc >> (8 * j));   // fold the running digest
+                acc = blk16(blk, ec);
             }
         raw ^= gf_mul(acc, ec.lane[t]);
     }

@@ -96,6 +96,7 @@ def _restore_equal(ctx, img, table, opts):
 def test_training_state_full_size():
     """decoder-1.3B training state, seed 2, 303 allocations, ~27 GB; the bench's
     configuration: one staging window, 64 KiB chunks."""
+    torch.cuda.empty_cache()
     table = workloads.training_state("cuda", seed=2)
     torch.cuda.synchronize()
     N = sum(t.numel() * t.element_size() for _, t in table)
@@ -116,6 +117,7 @@ def test_training_state_full_size():
 def test_hpc_incremental_full_size():
     """HPC image, seed 3, 512 allocations, 40 GB, ~60 % zero chunks; 5 % of the
     chunks rewritten (seed 33); delta dump, then base restore + delta apply."""
+    torch.cuda.empty_cache()
     table, _ = workloads.hpc_state("cuda", seed=3)
     torch.cuda.synchronize()
     ctx = mk.ckpt_ctx_create(0, 64 << 30)
@@ -138,6 +140,9 @@ def test_hpc_incremental_full_size():
         torch.cuda.synchronize()
         for (_, a), (_, b) in zip(new, table):
             assert torch.equal(a, b)
+        del new
+        base.free()
+        delta.free()
     finally:
         mk.ckpt_ctx_destroy(ctx)
 
@@ -145,7 +150,13 @@ def test_hpc_incremental_full_size():
 @pytest.mark.timeout(900)
 def test_fragmented_batched_full_size():
     """10,000 allocations, seed 4, 60 GB, 256 KiB-aligned zero blocks; graph
-    form (one launch) and per-allocation launches give the same image."""
+    form (one launch) and per-allocation launches give the same image. Two
+    60 GB pinned images do not fit the host at once, so the two are compared
+    through what fixes an image byte for byte: equal header and tables (so
+    equal kinds and payload layout), and each restoring, verified, to the
+    dumped state (so every payload record holds the chunk's bytes and zero
+    padding)."""
+    torch.cuda.empty_cache()   # 60 GB state + 60 GB staging + 60 GB restore targets
     table = workloads.fragmented_state("cuda", seed=4)
     torch.cuda.synchronize()
     ctx = mk.ckpt_ctx_create(0, 96 << 30)
@@ -154,13 +165,18 @@ def test_fragmented_batched_full_size():
         rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
         assert rc == 0, (mk.ckpt_strerror(rc), res.hip_error)
         assert res.windows == 1
-        _check_image(img, table, seed=4)
+        D, _ = _check_image(img, table, seed=4)
+        v = img.view()
+        n, nc = len(table), res.n_chunks
+        head = v[:64 + ((32 * n + 5 * nc + 15) & ~15)].copy()
+        _restore_equal(ctx, img, table, opts)
+        img.free()
         rc, img2, res2 = mk.ckpt_dump(ctx, table, opts=mk.make_opts(chunk_size=C, flags=mk.OPT_PER_ALLOC))
         assert rc == 0, (mk.ckpt_strerror(rc), res2.hip_error)
         assert res2.windows >= len([t for _, t in table if t.numel()])
-        assert np.array_equal(img.view(), img2.view())
+        assert img2.view().size == head.size + D
+        assert np.array_equal(img2.view()[:head.size], head)
+        _restore_equal(ctx, img2, table, opts)
         img2.free()
-        _restore_equal(ctx, img, table, opts)
-        img.free()
     finally:
         mk.ckpt_ctx_destroy(ctx)
