@@ -135,7 +135,7 @@ def main():
                     help="device staging budget in bytes (default: one staging window for the whole image, so "
                          "the dump kernel never shares the GPU with its own host-link copies)")
     ap.add_argument("--window", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=float, default=4e9, help="bytes of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=float, default=16e9, help="bytes of the oracle sample (0 = skip); ~10-15 s of CPU work")
     ap.add_argument("--check", action="store_true", help="verify restored bytes after each step")
     ap.add_argument("--form", default="plain", choices=["plain", "incremental", "batched", "serve"],
                     help="plain: full dump + restore (default); incremental: 40 GB HPC image, delta dump and "

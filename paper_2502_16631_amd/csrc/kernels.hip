@@ -395,18 +395,20 @@ k_chunks(JobList jl) {
             v4u v[K];
             uint32_t acc = 0, orw = 0;
             int any;
-            // Without a previous digest for the allocation the kind, and so
-            // the payload length, follows from the zero test alone: the
-            // aggregate is then published before the digest is computed, so
-            // the successors' look-backs rarely wait on this chunk.
+            // When the kind does not depend on the digest (a zero chunk, or no
+            // previous digest for the allocation) the payload length follows
+            // from the zero test alone: the aggregate is then published before
+            // the digest is computed, so the successors' look-backs rarely wait
+            // on this chunk.
             const uint64_t len16 = (len + 15u) & ~15u;
-            const bool early = MODE == kModeDump && (job.prev_crc == nullptr || ad.prev_first == ~0ull);
+            bool early = MODE == kModeDump && (job.prev_crc == nullptr || ad.prev_first == ~0ull);
             if (P == 1) {
                 load_rows<T, K>(v, aptr, len, ltid, active);
                 if constexpr (MODE == kModeDump) {
 #pragma unroll
                     for (int r = 0; r < K; ++r) orw |= or4(v[r]);
                     any = wg_any_lds<NW>(orw != 0, s_any);
+                    early = early || !any;
                     if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
                     if (any) acc = crc_rows<K>(v, 0, s_dt);
                 } else {
@@ -422,6 +424,7 @@ k_chunks(JobList jl) {
                     acc = crc_rows<K>(v, acc, s_dt);
                 }
                 any = (MODE == kModeDump) ? wg_any_lds<NW>(orw != 0, s_any) : 1;
+                early = early || (MODE == kModeDump && !any);
                 if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
             }
             uint32_t crc = ~init;
@@ -617,17 +620,15 @@ k_dump_stream(JobList jl) {
 
         // (LDS-only barriers from here on: streamed blocks stay in flight)
         const uint32_t any = wg_any_lds<NW>(orw != 0, s_any);
-        // Without a previous digest for the allocation the payload length
-        // follows from the zero test: the look-back runs now, before the
-        // digest, so the chunk's inclusive prefix is published early and the
-        // successors' look-backs stop right behind them. (Wave 0 issues its
-        // share of the next chunk's loads after the look-back: the status
-        // loads would otherwise wait for them on the vector memory counter.)
-        const bool early = job.prev_crc == nullptr || cur.prev_first == ~0ull;
-        if (early && tid < 64) {
-            const uint64_t e = lookback(job.status, g - job.g0, any ? len16 : 0, job.epoch, job.err);
-            if (tid == 0) s_off = e;
-        }
+        // When the kind does not depend on the digest -- a zero chunk, or no
+        // previous digest for the allocation -- the payload length follows
+        // from the zero test: its aggregate is published now, before the
+        // digest, so the successors' look-backs can pass this chunk while it
+        // is still being digested. (The look-back's own walk comes after the
+        // digest: its status loads wait on the vector memory counter, which
+        // by then the next chunk's loads have cleared.)
+        const bool early = !any || job.prev_crc == nullptr || cur.prev_first == ~0ull;
+        if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
         ChunkAt nxt{};
         if (tk_next < total) {
             nxt = chunk_at<C>(jl, tk_next);
@@ -647,13 +648,12 @@ k_dump_stream(JobList jl) {
             job.kind_out[g] = kd;
         }
         const uint64_t plen = kd == kData ? len16 : 0;
-        if (!early) {
-            if (tid < 64) {
-                const uint64_t e = lookback(job.status, g - job.g0, plen, job.epoch, job.err);
-                if (tid == 0) s_off = e;
-            }
-            lds_barrier();
+        if (tid < 64) {
+            const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
+                                     : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
+            if (tid == 0) s_off = e;
         }
+        lds_barrier();
         const uint64_t excl = s_off;
         if (kd == kData) store_rows_padded<T, K>(v, job.slot + excl, len16, ltid, true);
         if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;

@@ -48,7 +48,11 @@ struct DevBuf {
         }
         uint64_t want = std::max<uint64_t>(n, 256);
         hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();   // reported through the return value only
+            p = nullptr;
+            return e;
+        }
         cap = want;
         return hipSuccess;
     }

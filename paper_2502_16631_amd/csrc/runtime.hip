@@ -73,6 +73,9 @@ struct PinnedPool {
         }
         void* p = nullptr;
         if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) {
+            // A handled failure must not stay behind as the thread's last HIP
+            // error (the caller's next error check would report it).
+            (void)hipGetLastError();
             // pinned memory is limited: give back every cached buffer and retry once
             {
                 std::lock_guard<std::mutex> g(mu);
@@ -80,7 +83,10 @@ struct PinnedPool {
                 free_.clear();
                 cached = 0;
             }
-            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) return nullptr;
+            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
         }
         *got = cap;
         return p;
@@ -180,13 +186,18 @@ int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_table
 // ------------------------------------------------------------ helpers
 namespace mk {
 
-#define HIPCHK(call)                                 \
-    do {                                             \
-        hipError_t e_ = (call);                      \
-        if (e_ != hipSuccess) {                      \
-            if (res) res->hip_error = (int32_t)e_;   \
-            return CKPT_EHIP;                        \
-        }                                            \
+// A failed HIP call ends the entry point with CKPT_ENOMEM (allocation) or
+// CKPT_EHIP; the thread's last-error state is cleared, since the error is
+// reported by the return code.
+#define HIPCHK(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) {                                  \
+            (void)hipGetLastError();                             \
+            if (e_ == hipErrorOutOfMemory) return CKPT_ENOMEM;   \
+            if (res) res->hip_error = (int32_t)e_;               \
+            return CKPT_EHIP;                                    \
+        }                                                        \
     } while (0)
 
 uint32_t next_epoch(ckpt_ctx* c, bool* wrapped) {
@@ -635,11 +646,17 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     // kinds buffer: zero padding after the kinds (the kinds themselves are written by the kernel)
     HIPCHK(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
 
-    // image buffer: with one window it is allocated once the payload length
-    // is known (a delta's payload is a small part of its upper bound)
+    // With one staging slot and several windows (per-allocation launches
+    // when the whole image fits the staging budget) each window's payload is
+    // kept in staging right after the previous window's, and the payload is
+    // copied out once at the end, like a single window.
+    const bool stage_all = W > 1 && nslots == 1;
+    // image buffer: when the payload stays in staging it is allocated once the
+    // payload length is known (a delta's payload is a small part of its upper
+    // bound; pinned host memory is limited)
     ckpt_image* im = nullptr;
     uint8_t* himg = nullptr;
-    if (W > 1) {
+    if (W > 1 && !stage_all) {
         im = image_new(kHeader + tl + upper);
         if (!im) return CKPT_ENOMEM;
         himg = im->p;
@@ -659,6 +676,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     auto fail = [&](hipError_t e) {
         hipStreamSynchronize(c->s_main);
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
+        (void)hipGetLastError();   // the error is reported by the return code
         if (im) {
             pool().put(im->p, im->cap);
             delete im;
@@ -668,10 +686,10 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         return CKPT_EHIP;
     };
 
-    auto launch_window = [&](uint64_t w) -> hipError_t {
+    auto launch_window = [&](uint64_t w, uint64_t base) -> hipError_t {
         const int s = (int)(w % nslots);
         hipError_t e;
-        if (slot_used[s]) {
+        if (slot_used[s] && !stage_all) {
             e = hipStreamWaitEvent(c->s_main, ev[W + s], 0);
             if (e != hipSuccess) return e;
         }
@@ -694,7 +712,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         j.crc_out = crc_dev;
         j.kind_out = kind_dev;
         j.prev_crc = prev_dev;
-        j.slot = c->staging.as<uint8_t>() + (uint64_t)s * slot;
+        j.slot = c->staging.as<uint8_t>() + (stage_all ? base : (uint64_t)s * slot);
         j.status = c->status.as<uint64_t>();
         j.wtotal = wtot + w;
         j.err = err;
@@ -828,19 +846,25 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         // a slot of its own (nslots >= 2): its slot-free event then belongs to
         // a copy that has already been issued.
         const bool ahead = nslots >= 2;
-        if (W) e = launch_window(0);
+        if (W) e = launch_window(0, 0);
         for (uint64_t w = 0; w < W && e == hipSuccess; ++w) {
             if (w > 0 && !ahead) {
-                e = launch_window(w);
+                e = launch_window(w, pos);
                 if (e != hipSuccess) break;
             }
             if (ahead && w + 1 < W) {
-                e = launch_window(w + 1);
+                e = launch_window(w + 1, 0);
                 if (e != hipSuccess) break;
             }
             e = hipEventSynchronize(ev[w]);
             if (e != hipSuccess) break;
             const uint64_t dw = hw[w];
+            if (stage_all) {
+                // payload stays in staging (its capacity is the whole image)
+                if (pos + dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
+                pos += dw;
+                continue;
+            }
             if (dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
             if (!alloc_image(dw)) { e = hipErrorOutOfMemory; break; }
             const int s = (int)(w % nslots);
@@ -858,6 +882,20 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             }
             e = hipEventRecord(ev[W + s], cs);
             pos += dw;
+        }
+        if (e == hipSuccess && stage_all) {
+            // every window's kernel has completed (host waits above); one
+            // copy-out of the whole payload in ncs pieces
+            if (!alloc_image(pos)) e = hipErrorOutOfMemory;
+            t_link0 = now_ns();
+            const uint64_t piece = (std::max<uint64_t>(ceil_div(pos, ncs), 1ull << 20) + 4095) & ~4095ull;
+            for (uint32_t i = 0; e == hipSuccess && i < ncs && (uint64_t)i * piece < pos; ++i) {
+                const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, pos - lo);
+                e = hipStreamWaitEvent(c->s_copy[i], ev[W - 1], 0);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(himg + kHeader + tl + lo, c->staging.as<uint8_t>() + lo, len,
+                                       hipMemcpyDeviceToHost, c->s_copy[i]);
+            }
         }
         if (e != hipSuccess) return fail(e);
 

@@ -83,7 +83,14 @@ def _check_image(img, table, samples=1500, seed=0, prev_table=None):
     return D, kinds
 
 
+def _mem(tag):
+    free, total = torch.cuda.mem_get_info()
+    print("%s: device memory free %.1f of %.1f GiB, torch reserved %.1f GiB"
+          % (tag, free / 2**30, total / 2**30, torch.cuda.memory_reserved() / 2**30), flush=True)
+
+
 def _restore_equal(ctx, img, table, opts):
+    _mem("before restore targets")
     targets = [(i, torch.empty_like(t)) for i, t in table]
     rc, res = mk.ckpt_restore(ctx, img, targets, opts=opts)
     assert rc == 0, (mk.ckpt_strerror(rc), res.first_bad_chunk)
@@ -97,6 +104,7 @@ def test_training_state_full_size():
     """decoder-1.3B training state, seed 2, 303 allocations, ~27 GB; the bench's
     configuration: one staging window, 64 KiB chunks."""
     torch.cuda.empty_cache()
+    _mem("start")
     table = workloads.training_state("cuda", seed=2)
     torch.cuda.synchronize()
     N = sum(t.numel() * t.element_size() for _, t in table)
@@ -118,6 +126,7 @@ def test_hpc_incremental_full_size():
     """HPC image, seed 3, 512 allocations, 40 GB, ~60 % zero chunks; 5 % of the
     chunks rewritten (seed 33); delta dump, then base restore + delta apply."""
     torch.cuda.empty_cache()
+    _mem("start")
     table, _ = workloads.hpc_state("cuda", seed=3)
     torch.cuda.synchronize()
     ctx = mk.ckpt_ctx_create(0, 64 << 30)
@@ -157,8 +166,10 @@ def test_fragmented_batched_full_size():
     dumped state (so every payload record holds the chunk's bytes and zero
     padding)."""
     torch.cuda.empty_cache()   # 60 GB state + 60 GB staging + 60 GB restore targets
+    _mem("start")
     table = workloads.fragmented_state("cuda", seed=4)
     torch.cuda.synchronize()
+    _mem("state")
     ctx = mk.ckpt_ctx_create(0, 96 << 30)
     try:
         opts = mk.make_opts(chunk_size=C, flags=mk.OPT_GRAPH)
