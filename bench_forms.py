@@ -80,7 +80,8 @@ def incremental(args, torch, mk, link):
         "delta_link_GBps": round(info["link_bytes"] / td / 1e9, 2),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
         "roofline": {"bound": "hbm", "achieved": round(alg / k_avg / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(alg / k_avg / 1e9 / 8000.0, 4), "kernel": "k_chunks dump mode (delta)"},
+                     "frac": round(alg / k_avg / 1e9 / 8000.0, 4),
+                     "kernel": "delta dump stage: digest+kind pass, offsets scan, gather (one window)"},
     }
 
 
@@ -151,14 +152,16 @@ def batched(args, torch, mk, link):
 
 def serve(args, torch, mk, link):
     """32 tenants with device states log-uniform in [100 MB, 8 GB] (scaled to
-    ~48 GB in total; kinds cycle DL-like / HPC-like / random), Poisson
+    ~24 GB in total, so that every tenant's last image and the images of
+    the requests in flight fit the host's pinned-memory limit (64 GiB on the
+    machines measured); kinds cycle DL-like / HPC-like / random), Poisson
     arrivals at `rate` requests per second for `duration` seconds, uniform
     tenant, 50 % dumps (half of them incremental after 5 % of the tenant's
     chunks were rewritten) and 50 % restores of the tenant's last image; a
     tenant's requests run one at a time. Latency is arrival to completion."""
     rng = np.random.default_rng(5)
     n_t = 32
-    sizes = workloads.loguniform_sizes(n_t, 100 * 10**6, 8 * 10**9, int(48e9 * args.scale), 1 << 20, seed=5)
+    sizes = workloads.loguniform_sizes(n_t, 100 * 10**6, 8 * 10**9, int(24e9 * args.scale), 1 << 20, seed=5)
     tenants = []
     for t, size in enumerate(sizes):
         kind = t % 3
@@ -171,7 +174,8 @@ def serve(args, torch, mk, link):
             table, _ = workloads.hpc_state("cuda", seed=100 + t, total=size, n=8, chunk=C)
         else:               # random bytes with zero blocks
             table = workloads.fragmented_state("cuda", seed=100 + t, total=size, n=16)
-        tenants.append({"table": table, "N": _nbytes(table), "last": None, "busy": None, "backlog": []})
+        tenants.append({"table": table, "N": _nbytes(table), "last": None, "busy": None, "backlog": [],
+                        "stale": False})
     torch.cuda.synchronize()
     N_all = sum(t["N"] for t in tenants)
     ctx = mk.ckpt_ctx_create(0, 64 << 30)
@@ -191,6 +195,7 @@ def serve(args, torch, mk, link):
         r = rng.random()
         arrivals.append((tt, int(rng.integers(0, n_t)), "restore" if r < 0.5 else ("delta" if r < 0.75 else "full")))
     lat, done_bytes, n_done, n_fail = [], 0, 0, 0
+    fail_codes = {}
     kinds_done = {"restore": 0, "delta": 0, "full": 0}
     inflight = {}
     t_start = time.perf_counter()
@@ -199,6 +204,9 @@ def serve(args, torch, mk, link):
 
     def submit(tid, kind, t_arr):
         ten = tenants[tid]
+        if ten["stale"]:
+            # a failed dump left the state ahead of the last image: take a full one
+            kind = "full"
         if kind == "restore":
             rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, ten["table"], img=ten["last"], tenant=tid)
         else:
@@ -231,6 +239,9 @@ def serve(args, torch, mk, link):
             lat.append(time.perf_counter() - t_start - t_arr)
             if rc != 0:
                 n_fail += 1
+                if kind != "restore":
+                    ten["stale"] = True
+                fail_codes[mk.ckpt_strerror(rc)] = fail_codes.get(mk.ckpt_strerror(rc), 0) + 1
             else:
                 n_done += 1
                 kinds_done[kind] += 1
@@ -238,6 +249,7 @@ def serve(args, torch, mk, link):
                 if img is not None:
                     old_images.append(ten["last"])
                     ten["last"] = img
+                    ten["stale"] = False
             if ten["backlog"]:
                 k2, ta2 = ten["backlog"].pop(0)
                 submit(tid, k2, ta2)
@@ -255,7 +267,8 @@ def serve(args, torch, mk, link):
         "config": {"workload": "%d tenants, %.1f GB of device state, Poisson %.1f req/s for %.0f s"
                                % (n_t, N_all / 1e9, args.rate, args.duration), "chunk": C,
                    "staging_budget": 64 << 30, "max_active": 16},
-        "requests": len(arrivals), "completed": n_done, "failed": n_fail, "by_kind": kinds_done,
+        "requests": len(arrivals), "completed": n_done, "failed": n_fail, "fail_codes": fail_codes,
+        "by_kind": kinds_done,
         "latency_p50_ms": round(_pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(_pct(lat, 99) * 1e3, 2),
         "server_p50_ms": round(st.p50_ns / 1e6, 2), "server_p99_ms": round(st.p99_ns / 1e6, 2),
         "server_mean_wait_ms": round(st.mean_wait_ns / 1e6, 2),

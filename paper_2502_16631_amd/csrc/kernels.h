@@ -5,7 +5,11 @@
 
 namespace mk {
 
-enum Mode : int { kModeDump = 0, kModeDigest = 1, kModeVerify = 2, kModeRestore = 3 };
+// classify: digest and kind of every chunk, nothing else (first pass of a
+// two-pass dump); gather: DATA chunks to their payload records at off[g]
+// (its last pass, after the offsets scan).
+enum Mode : int { kModeDump = 0, kModeDigest = 1, kModeVerify = 2, kModeRestore = 3, kModeClassify = 4,
+                  kModeGather = 5 };
 
 // One launch of the chunk engine over global chunks [g0, g1).
 struct ChunkJob {
@@ -15,14 +19,14 @@ struct ChunkJob {
     const uint32_t* amap;        // allocation of chunk g at [g], or nullptr (binary search)
     uint64_t g0, g1;
     const EngineConsts* ec;      // tables for (T, C)
-    uint32_t* crc_out;           // dump / digest: digest of chunk g at [g]
-    uint8_t* kind_out;           // dump: kind of chunk g at [g]
-    const uint8_t* kind_in;      // verify / restore: kind of chunk g
+    uint32_t* crc_out;           // dump / digest / classify: digest of chunk g at [g]
+    uint8_t* kind_out;           // dump / classify: kind of chunk g at [g]
+    const uint8_t* kind_in;      // verify / restore / gather: kind of chunk g
     const uint32_t* ref_crc;     // verify / restore: expected digest of chunk g
-    const uint32_t* prev_crc;    // dump: previous digest table or nullptr
-    uint8_t* slot;               // staging window (dump: written, restore: read)
-    const uint64_t* off;         // restore: payload offset of chunk g
-    uint64_t slot_base;          // restore: payload offset of the window start
+    const uint32_t* prev_crc;    // dump / classify: previous digest table or nullptr
+    uint8_t* slot;               // staging window (dump, gather: written; restore: read)
+    const uint64_t* off;         // restore / gather: payload offset of chunk g
+    uint64_t slot_base;          // restore / gather: payload offset of the window start
     uint64_t* status;            // dump: look-back status, indexed by g - g0
     uint64_t* wtotal;            // dump: payload bytes of the window
     unsigned long long* bad;     // verify / restore: lowest failing chunk (init ~0)

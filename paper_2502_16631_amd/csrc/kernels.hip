@@ -347,10 +347,11 @@ k_chunks(JobList jl) {
         asm volatile("" : "+v"(lc), "+v"(ltid));
 
         uint8_t kd_in = kData;
-        if constexpr (MODE == kModeVerify || MODE == kModeRestore) {
+        if constexpr (MODE == kModeVerify || MODE == kModeRestore || MODE == kModeGather) {
             kd_in = job.kind_in[g];
             if (MODE == kModeVerify && kd_in != kUnchanged) continue;
             if (MODE == kModeRestore && kd_in == kUnchanged) continue;
+            if (MODE == kModeGather && kd_in != kData) continue;
         }
         const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);
         const AllocDesc ad = job.allocs[a];
@@ -361,7 +362,20 @@ k_chunks(JobList jl) {
         const uint32_t init = full ? full_init : ad.tail_init;
         uint8_t* const aptr = reinterpret_cast<uint8_t*>(ad.ptr) + (k << log2c);
 
-        if constexpr (MODE == kModeRestore) {
+        if constexpr (MODE == kModeGather) {
+            // a DATA chunk to its payload record (whole 16-byte blocks, the
+            // padding past len zero)
+            const uint64_t len16 = (len + 15u) & ~15u;
+            uint8_t* dst = job.slot + (job.off[g] - job.slot_base);
+            for (uint32_t p = 0; p < P; ++p) {
+                const uint64_t lp = (uint64_t)p * TILE;
+                if (lp >= len16) break;
+                v4u v[K];
+                load_rows<T, K>(v, aptr + lp, len - lp, ltid, active);
+                store_rows_padded<T, K>(v, dst + lp, len16 - lp, ltid, active);
+            }
+            continue;
+        } else if constexpr (MODE == kModeRestore) {
             if (kd_in == kZero) {
                 const v4u z = vzero();
                 v4u zv[K];
@@ -404,12 +418,14 @@ k_chunks(JobList jl) {
             bool early = MODE == kModeDump && (job.prev_crc == nullptr || ad.prev_first == ~0ull);
             if (P == 1) {
                 load_rows<T, K>(v, aptr, len, ltid, active);
-                if constexpr (MODE == kModeDump) {
+                if constexpr (MODE == kModeDump || MODE == kModeClassify) {
 #pragma unroll
                     for (int r = 0; r < K; ++r) orw |= or4(v[r]);
                     any = wg_any_lds<NW>(orw != 0, s_any);
-                    early = early || !any;
-                    if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
+                    if constexpr (MODE == kModeDump) {
+                        early = early || !any;
+                        if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
+                    }
                     if (any) acc = crc_rows<K>(v, 0, s_dt);
                 } else {
                     any = 1;
@@ -423,7 +439,7 @@ k_chunks(JobList jl) {
                     for (int r = 0; r < K; ++r) orw |= or4(v[r]);
                     acc = crc_rows<K>(v, acc, s_dt);
                 }
-                any = (MODE == kModeDump) ? wg_any_lds<NW>(orw != 0, s_any) : 1;
+                any = (MODE == kModeDump || MODE == kModeClassify) ? wg_any_lds<NW>(orw != 0, s_any) : 1;
                 early = early || (MODE == kModeDump && !any);
                 if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
             }
@@ -435,6 +451,18 @@ k_chunks(JobList jl) {
             }
             if constexpr (MODE == kModeDigest) {
                 if (tid == 0) job.crc_out[g] = crc;
+                continue;
+            }
+            if constexpr (MODE == kModeClassify) {
+                // digest and kind only; offsets and payload come from later passes
+                uint8_t kd = kData;
+                if (!any) kd = kZero;
+                else if (job.prev_crc != nullptr && ad.prev_first != ~0ull && job.prev_crc[ad.prev_first + k] == crc)
+                    kd = kUnchanged;
+                if (tid == 0) {
+                    job.crc_out[g] = crc;
+                    job.kind_out[g] = kd;
+                }
                 continue;
             }
             if constexpr (MODE == kModeVerify) {
@@ -538,7 +566,10 @@ typedef __attribute__((address_space(1))) void glb_void;
 // the next one (being streamed) and the one after (a value only); every
 // ticket below its current one is held by a running work-group, so
 // look-back waits end.
-template <int T, int K>
+//
+// With CLASSIFY the kernel is the first pass of a two-pass dump: digest and
+// kind of every chunk, no look-back and no payload.
+template <int T, int K, bool CLASSIFY>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4)))
 k_dump_stream(JobList jl) {
     static_assert(T >= 64 && T % 64 == 0, "whole waves");
@@ -628,7 +659,7 @@ k_dump_stream(JobList jl) {
         // digest: its status loads wait on the vector memory counter, which
         // by then the next chunk's loads have cleared.)
         const bool early = !any || job.prev_crc == nullptr || cur.prev_first == ~0ull;
-        if (early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
+        if (!CLASSIFY && early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
         ChunkAt nxt{};
         if (tk_next < total) {
             nxt = chunk_at<C>(jl, tk_next);
@@ -647,16 +678,18 @@ k_dump_stream(JobList jl) {
             job.crc_out[g] = crc;
             job.kind_out[g] = kd;
         }
-        const uint64_t plen = kd == kData ? len16 : 0;
-        if (tid < 64) {
-            const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
-                                     : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
-            if (tid == 0) s_off = e;
+        if constexpr (!CLASSIFY) {
+            const uint64_t plen = kd == kData ? len16 : 0;
+            if (tid < 64) {
+                const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
+                                         : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
+                if (tid == 0) s_off = e;
+            }
+            lds_barrier();
+            const uint64_t excl = s_off;
+            if (kd == kData) store_rows_padded<T, K>(v, job.slot + excl, len16, ltid, true);
+            if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
         }
-        lds_barrier();
-        const uint64_t excl = s_off;
-        if (kd == kData) store_rows_padded<T, K>(v, job.slot + excl, len16, ltid, true);
-        if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
         tk = tk_next;
         cur = nxt;
     }
@@ -806,15 +839,25 @@ hipError_t launch_tk(int mode, const JobList& jl, int grid, hipStream_t s) {
         case kModeDump:
             if constexpr (T >= 64) {
                 if (jl.job[0].C == 16u * T * K) {
-                    hipLaunchKernelGGL((k_dump_stream<T, K>), dim3(grid), dim3(T), 0, s, jl);
+                    hipLaunchKernelGGL((k_dump_stream<T, K, false>), dim3(grid), dim3(T), 0, s, jl);
                     break;
                 }
             }
             hipLaunchKernelGGL((k_chunks<T, K, kModeDump>), dim3(grid), dim3(NT), 0, s, jl);
             break;
+        case kModeClassify:
+            if constexpr (T >= 64) {
+                if (jl.job[0].C == 16u * T * K) {
+                    hipLaunchKernelGGL((k_dump_stream<T, K, true>), dim3(grid), dim3(T), 0, s, jl);
+                    break;
+                }
+            }
+            hipLaunchKernelGGL((k_chunks<T, K, kModeClassify>), dim3(grid), dim3(NT), 0, s, jl);
+            break;
         case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, jl); break;
+        case kModeGather: hipLaunchKernelGGL((k_chunks<T, K, kModeGather>), dim3(grid), dim3(NT), 0, s, jl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -830,7 +873,16 @@ hipError_t occ_tk(int mode, int* n) {
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDump>, NT, 0);
             if constexpr (T >= 64) {
                 int m = 0;
-                if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_dump_stream<T, K>, T, 0);
+                if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_dump_stream<T, K, false>, T, 0);
+                if (e == hipSuccess && m < *n) *n = m;
+            }
+            return e;
+        }
+        case kModeClassify: {
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeClassify>, NT, 0);
+            if constexpr (T >= 64) {
+                int m = 0;
+                if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_dump_stream<T, K, true>, T, 0);
                 if (e == hipSuccess && m < *n) *n = m;
             }
             return e;
@@ -838,6 +890,7 @@ hipError_t occ_tk(int mode, int* n) {
         case kModeDigest: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDigest>, NT, 0);
         case kModeVerify: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeVerify>, NT, 0);
         case kModeRestore: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeRestore>, NT, 0);
+        case kModeGather: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeGather>, NT, 0);
         default: return hipErrorInvalidValue;
     }
 }

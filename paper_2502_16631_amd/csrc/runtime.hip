@@ -614,8 +614,9 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     for (const Window& w : wins) max_win = std::max(max_win, w.g1 - w.g0);
     HIPCHK(c->status.ensure(8 * (max_win + 64)));
     const uint64_t W = wins.size();
-    // ctl: tickets[W] | wtot[W] (u64) | err
-    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (W + 1)), ctl_err = ctl_wt + 8 * (W + 1);
+    // ctl: tickets[max(W, 3) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
+    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (std::max<uint64_t>(W, 3) + 1)),
+                   ctl_err = ctl_wt + 8 * (W + 1), ctl_cnt = ctl_err + 16;
     HIPCHK(c->ctl.ensure(ctl_err + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
     HIPCHK(ensure_events(c, W + (size_t)nslots + 2));
@@ -639,6 +640,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     uint32_t* tickets = reinterpret_cast<uint32_t*>(ctl + ctl_tk);
     uint64_t* wtot = reinterpret_cast<uint64_t*>(ctl + ctl_wt);
     uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
+    unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctl + ctl_cnt);
     HIPCHK(c->amap.ensure(4 * std::max<uint64_t>(nc, 1)));
     HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice, c->s_main));
     HIPCHK(launch_chunk_map(c->descs.as<AllocDesc>(), n, C, c->amap.as<uint32_t>(), c->s_main));
@@ -734,6 +736,70 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     const uint64_t len_a = 32ull * n + 4 * nc, len_b = tl - len_a;
     uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall + 8 * (W + 1));
     const bool use_graph = o && (o->flags & CKPT_OPT_GRAPH) && W == 1 && !per_alloc;
+    // A delta dump in one window takes three passes: digests and kinds of
+    // every chunk, the payload offsets (scan over the kinds), then the DATA
+    // chunks gathered to their records. A delta's kinds depend on the
+    // digests, so a single pass would hold every chunk's look-back until its
+    // digest is done; its payload is small, so the extra read of D costs
+    // little.
+    const bool two_pass = prev != nullptr && W == 1 && !use_graph && nc > 0;
+    auto launch_two_pass = [&]() -> hipError_t {
+        hipError_t e;
+        bool wrapped;
+        const uint32_t ep = next_epoch(c, &wrapped);
+        if (wrapped && (e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main)) != hipSuccess)
+            return e;
+        if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
+        if ((e = c->wb.ensure(16)) != hipSuccess) return e;
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = c->descs.as<AllocDesc>();
+        j.n_allocs = n;
+        j.C = C;
+        j.amap = c->amap.as<uint32_t>();
+        j.g0 = 0;
+        j.g1 = nc;
+        j.ec = ec;
+        j.crc_out = crc_dev;
+        j.kind_out = kind_dev;
+        j.kind_in = kind_dev;
+        j.prev_crc = prev_dev;
+        j.slot = c->staging.as<uint8_t>();
+        j.off = c->off.as<uint64_t>();
+        j.slot_base = 0;
+        j.err = err;
+        j.epoch = ep;
+        int grid;
+        if ((e = grid_for(c, T, K, kModeClassify, nc, &grid)) != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[0], c->s_main)) != hipSuccess) return e;
+        if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 0), grid, c->s_main)) != hipSuccess) return e;
+        OffJob oj;
+        memset(&oj, 0, sizeof(oj));
+        oj.allocs = c->descs.as<AllocDesc>();
+        oj.n_allocs = n;
+        oj.C = C;
+        oj.amap = c->amap.as<uint32_t>();
+        oj.n_chunks = nc;
+        oj.kind = kind_dev;
+        oj.off = c->off.as<uint64_t>();
+        oj.per_window = nc + 1;
+        oj.wb = c->wb.as<uint64_t>();
+        oj.n_windows = 1;
+        oj.status = c->status.as<uint64_t>();
+        oj.ticket = tickets + 1;
+        oj.counts = counts;
+        oj.err = err;
+        oj.epoch = ep;
+        const uint64_t tiles = ceil_div(nc, 256);
+        if ((e = launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main)) != hipSuccess)
+            return e;
+        if ((e = grid_for(c, T, K, kModeGather, nc, &grid)) != hipSuccess) return e;
+        if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2), grid, c->s_main)) != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(hw, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+            return e;
+        return hipEventRecord(ev[0], c->s_main);
+    };
     if (use_graph) {
         // ---- batched form: the whole device stage as one captured graph
         uint64_t key = 1469598103934665603ull;
@@ -846,7 +912,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         // a slot of its own (nslots >= 2): its slot-free event then belongs to
         // a copy that has already been issued.
         const bool ahead = nslots >= 2;
-        if (W) e = launch_window(0, 0);
+        if (W) e = two_pass ? launch_two_pass() : launch_window(0, 0);
         for (uint64_t w = 0; w < W && e == hipSuccess; ++w) {
             if (w > 0 && !ahead) {
                 e = launch_window(w, pos);

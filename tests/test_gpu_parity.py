@@ -186,6 +186,17 @@ def test_delta_dump_merge_and_in_place_restore(ctx):
     b_img, b_or, _ = check_parity(ctx, base, c)
     d_img, d_or, res = check_parity(ctx, new, c, prev_gpu=b_img, prev_oracle=b_or)
     assert res.n_unchanged > 0
+    # the same delta through every launch form: one window (three passes:
+    # digests and kinds, offsets, gather), several windows and a captured
+    # graph (single pass with look-back), one launch per allocation
+    for kw in (dict(window_bytes=4 * c), dict(flags=mk.OPT_GRAPH), dict(flags=mk.OPT_PER_ALLOC),
+               dict(flags=mk.OPT_PER_ALLOC, window_bytes=2 * c)):
+        check_parity(ctx, new, c, prev_gpu=b_img, prev_oracle=b_or, **kw)
+    # other chunk sizes: a streamed tile shape (16 KiB) and several passes per chunk (256 KiB)
+    for c2 in (16384, 262144):
+        b2, bo2, _ = check_parity(ctx, base, c2)
+        check_parity(ctx, new, c2, prev_gpu=b2, prev_oracle=bo2)
+        check_parity(ctx, new, c2, prev_gpu=b2, prev_oracle=bo2, window_bytes=4 * c2)
     # same delta when the previous image is not resident (imported copy)
     rc, b_imp = mk.ckpt_image_import(b_img.view())
     assert rc == 0
