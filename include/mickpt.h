@@ -2,7 +2,8 @@
  * mickpt.h -- C ABI of the MI355X checkpoint-image engine (libmickpt.so).
  *
  * The library turns a process's set of device allocations into a verified,
- * restorable memory image in pinned host memory, and writes such an image
+ * restorable memory image in host memory (pinned while the driver grants
+ * pinned memory, pageable beyond that), and writes such an image
  * back byte for byte. It follows the problem statement of transparent GPU
  * checkpointing (CRIUgpu, arXiv 2502.16631):
  *   - section 3.1.1: the checkpoint action copies the GPU state (device
@@ -36,7 +37,7 @@ extern "C" {
 #define CKPT_OK         0
 #define CKPT_EINVAL    -1  /* bad argument: NULL, chunk size not a power of two in [16, 2^30],
                               duplicate ids, misaligned device pointer, unknown flag          */
-#define CKPT_ENOMEM    -2  /* device staging, pinned host or descriptor allocation failed, or
+#define CKPT_ENOMEM    -2  /* device staging, host image or descriptor allocation failed, or
                               the request does not fit the staging budget                     */
 #define CKPT_EHIP      -3  /* a HIP call failed (ckpt_result.hip_error holds its code) or a
                               kernel reported an internal error                               */
@@ -72,7 +73,7 @@ typedef struct {
 } ckpt_alloc_table;
 
 typedef struct ckpt_ctx ckpt_ctx;       /* device context: staging, streams, digest cache */
-typedef struct ckpt_image ckpt_image;   /* an image in pinned host memory                 */
+typedef struct ckpt_image ckpt_image;   /* an image in host memory (pinned if available)  */
 
 /* Tuning knobs. None of them changes the bytes of an image except
  * chunk_size, which is recorded in its header. Pass NULL for defaults. */

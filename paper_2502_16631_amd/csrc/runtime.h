@@ -99,12 +99,14 @@ inline uint64_t get64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v
 
 }  // namespace mk
 
-// An image in pinned host memory.
+// An image in host memory: pinned when the driver grants it (the pinned
+// pool), else pageable (copies through it are slower).
 struct ckpt_image {
     uint8_t* p = nullptr;
     uint64_t n = 0;
     uint64_t cap = 0;
     uint64_t uid = 0;   // identity: key of the image's resident digest table
+    bool pinned = true;
 };
 
 struct ckpt_ctx {
@@ -134,6 +136,7 @@ struct ckpt_ctx {
 namespace mk {
 
 ckpt_image* image_new(uint64_t cap);
+void image_release(ckpt_image* im);   // returns the memory (pool or heap) and deletes im
 uint32_t next_epoch(ckpt_ctx* c, bool* wrapped);
 void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K);
 hipError_t get_consts(ckpt_ctx* c, int T, uint32_t C, const EngineConsts** out);

@@ -116,11 +116,29 @@ PinnedPool& pool() {
 ckpt_image* mk::image_new(uint64_t cap) {
     ckpt_image* im = new ckpt_image();
     uint64_t got = 0;
-    im->p = static_cast<uint8_t*>(pool().get(cap, &got));
-    if (!im->p) { delete im; return nullptr; }
+    // MICKPT_HOST_PAGEABLE set: every image in pageable memory (exercises the
+    // fallback below without exhausting pinned memory)
+    if (!getenv("MICKPT_HOST_PAGEABLE")) im->p = static_cast<uint8_t*>(pool().get(cap, &got));
+    if (!im->p) {
+        // the driver limits pinned memory per process (64 GiB on the MI355X
+        // hosts measured): fall back to pageable memory, which the copy
+        // engines reach through the runtime's own staging
+        got = (std::max<uint64_t>(cap, 1) + 4095) & ~4095ull;
+        void* q = nullptr;
+        if (posix_memalign(&q, 4096, got) != 0) { delete im; return nullptr; }
+        im->p = static_cast<uint8_t*>(q);
+        im->pinned = false;
+    }
     im->cap = got;
     im->uid = g_uid.fetch_add(1);
     return im;
+}
+
+void mk::image_release(ckpt_image* im) {
+    if (!im) return;
+    if (im->pinned) pool().put(im->p, im->cap);
+    else free(im->p);
+    delete im;
 }
 
 // ------------------------------------------------------------ parsed image
@@ -679,10 +697,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         hipStreamSynchronize(c->s_main);
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
         (void)hipGetLastError();   // the error is reported by the return code
-        if (im) {
-            pool().put(im->p, im->cap);
-            delete im;
-        }
+        if (im) image_release(im);
         if (e == hipErrorOutOfMemory) return CKPT_ENOMEM;
         if (res) res->hip_error = (int32_t)e;
         return CKPT_EHIP;
@@ -1407,11 +1422,7 @@ extern "C" int ckpt_image_import(const void* p, uint64_t n, ckpt_image** out) {
     return CKPT_OK;
 }
 
-extern "C" void ckpt_image_free(ckpt_image* img) {
-    if (!img) return;
-    pool().put(img->p, img->cap);
-    delete img;
-}
+extern "C" void ckpt_image_free(ckpt_image* img) { image_release(img); }
 
 extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_image** out) {
     if (!out) return CKPT_EINVAL;

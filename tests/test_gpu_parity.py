@@ -254,3 +254,22 @@ def test_error_paths_match_the_oracle(ctx):
     rc, res = mk.ckpt_restore(ctx, d_img, wrong)
     want = corc.restore(d_or, [(i, np.full(t.numel(), 3, np.uint8)) for i, t in table])
     assert (rc, res.first_bad_chunk) == want and rc == mk.CKPT_EBASE
+
+
+def test_pageable_host_images(ctx):
+    """Images in pageable host memory (the fallback once the driver's pinned
+    memory is used up) dump and restore exactly as pinned ones."""
+    c = 65536
+    rng = np.random.default_rng(31)
+    gen = torch.Generator(device=DEV).manual_seed(31)
+    table = _rand_table(rng, gen, 12, c, max_chunks=8)
+    os.environ["MICKPT_HOST_PAGEABLE"] = "1"
+    try:
+        img, oimg, _ = check_parity(ctx, table, c)
+        restore_and_compare(ctx, img, table)
+        new = [(i, t.clone()) for i, t in table]
+        workloads.mutate_runs(new, seed=32, chunk=c, frac=0.3, run_mean=2)
+        check_parity(ctx, new, c, prev_gpu=img, prev_oracle=oimg)
+        check_parity(ctx, table, c, window_bytes=2 * c)
+    finally:
+        del os.environ["MICKPT_HOST_PAGEABLE"]
