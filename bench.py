@@ -119,9 +119,22 @@ def cpu_baseline(table, chunk, budget_bytes):
     rc, img = oracle.dump(host, chunk, threads=threads)
     dt = time.perf_counter() - t0
     assert rc == 0
+    del img
+    # one thread, on the first allocations up to 1 GB of the same sample
+    one, n1 = [], 0
+    for i, a in host:
+        if n1 and n1 + a.size > 1e9:
+            break
+        one.append((i, a))
+        n1 += a.size
+    t1 = time.perf_counter()
+    rc, _ = oracle.dump(one, chunk, threads=1)
+    d1 = time.perf_counter() - t1
+    assert rc == 0
     return {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "full dump of %d of the workload's allocations (%.2f GB), %d threads, %.1f s"
-                      % (len(sample), total / 1e9, threads, dt)}
+                      % (len(sample), total / 1e9, threads, dt),
+            "single_thread_GBps": round(n1 / d1 / 1e9, 3)}
 
 
 def main():
@@ -137,10 +150,11 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--cpu-sample", type=float, default=16e9, help="bytes of the oracle sample (0 = skip); ~10-15 s of CPU work")
     ap.add_argument("--check", action="store_true", help="verify restored bytes after each step")
-    ap.add_argument("--form", default="plain", choices=["plain", "incremental", "batched", "serve"],
+    ap.add_argument("--form", default="plain", choices=["plain", "incremental", "batched", "serve", "ondemand"],
                     help="plain: full dump + restore (default); incremental: 40 GB HPC image, delta dump and "
                          "base + delta restore; batched: 10,000 allocations, graph-captured single launch vs "
-                         "per-allocation launches, autotuned; serve: multi-tenant Poisson trace, p50/p99")
+                         "per-allocation launches, autotuned; serve: multi-tenant Poisson trace, p50/p99; "
+                         "ondemand: parameters restored first vs one full restore")
     ap.add_argument("--scale", type=float, default=1.0, help="scale the total bytes of the non-plain forms")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: aggregate requests per second")
@@ -156,7 +170,8 @@ def main():
     if args.form != "plain":
         import bench_forms
         line = {"incremental": bench_forms.incremental, "batched": bench_forms.batched,
-                "serve": bench_forms.serve}[args.form](args, torch, mk, link_baseline(torch))
+                "serve": bench_forms.serve, "ondemand": bench_forms.ondemand}[args.form](
+                    args, torch, mk, link_baseline(torch))
         print(json.dumps(line), flush=True)
         return
 

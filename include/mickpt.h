@@ -141,6 +141,19 @@ int  ckpt_dump(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* p
 int  ckpt_restore(ckpt_ctx* ctx, const ckpt_image* img, const ckpt_alloc_table* table,
                   const ckpt_opts* opts, void* stream, ckpt_result* res);
 
+/* On-demand restore (section 5.2 names on-demand restore among the ways to
+ * cut restore time; section 7 cites on-demand checkpoint/restore of GPU
+ * applications). Like ckpt_restore, but `table` lists only the allocations
+ * wanted now, each matched to the image's allocation with the same id (any
+ * order; sizes must match: CKPT_EMISMATCH for an unknown id or another
+ * size; CKPT_EINVAL for an id listed twice). Only those allocations' payload
+ * crosses the link and only their memory is written and verified; the rest
+ * can follow in later calls. For a delta image the UNCHANGED chunks of the
+ * listed allocations must hold the base state (CKPT_EBASE). ckpt_result
+ * reports the logical and payload bytes of the listed allocations. */
+int  ckpt_restore_some(ckpt_ctx* ctx, const ckpt_image* img, const ckpt_alloc_table* table,
+                       const ckpt_opts* opts, void* stream, ckpt_result* res);
+
 /* ------------------------------------------------------------------ autotuner */
 /* Batched form: choose chunk size (16, 64 or 256 KiB), work-group width and
  * copy-stream count for `table` by timing trial dumps of a bounded sample of

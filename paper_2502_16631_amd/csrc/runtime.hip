@@ -1061,8 +1061,12 @@ extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_
 }
 
 // ------------------------------------------------------------ restore
+// Restore. With `some` false the table is the image's whole table, in order
+// (EMISMATCH otherwise). With `some` true it lists a subset of the image's
+// allocations by id, in any order (on-demand restore): only their chunks
+// are moved, verified and written; the others' memory is never touched.
 static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
-                        void* stream, ckpt_result* res) {
+                        void* stream, ckpt_result* res, bool some) {
     const uint64_t t_start = now_ns();
     if (o && (o->reserved || (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING))))
         return CKPT_EINVAL;
@@ -1074,24 +1078,48 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     const uint32_t C = v.C;
     const uint64_t nc = v.n_chunks, tl = v.tl;
     const uint64_t len_a = 32ull * v.n_allocs + 4 * nc, len_b = tl - len_a;
-    for (uint32_t a = 0; a < n && a < v.n_allocs; ++a) {
+    for (uint32_t a = 0; a < n && (some || a < v.n_allocs); ++a) {
         const ckpt_alloc& e = table->v[a];
         if (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15))) return CKPT_EINVAL;
+    }
+    // sel[a]: the table entry restored into image allocation a, or -1
+    std::vector<int64_t> sel(v.n_allocs, -1);
+    if (some) {
+        std::unordered_map<uint64_t, uint64_t> where;
+        where.reserve(2 * v.n_allocs + 1);
+        for (uint64_t a = 0; a < v.n_allocs; ++a) where.emplace(get64(v.recs + 32 * a), a);
+        for (uint32_t i = 0; i < n; ++i) {
+            auto it = where.find(table->v[i].id);
+            if (it == where.end()) continue;                 // EMISMATCH after validation
+            if (sel[it->second] >= 0) return CKPT_EINVAL;   // the same id twice
+            sel[it->second] = i;
+        }
+    } else {
+        for (uint64_t a = 0; a < v.n_allocs && a < n; ++a) sel[a] = (int64_t)a;
     }
     // descriptors from the image's records (sizes, grid) and the caller's pointers
     std::vector<AllocDesc> d(v.n_allocs);
     for (uint64_t a = 0; a < v.n_allocs; ++a) {
         const uint8_t* r = v.recs + 32 * a;
-        const void* ptr = a < n ? table->v[a].dev_ptr : nullptr;
+        const void* ptr = sel[a] >= 0 ? table->v[sel[a]].dev_ptr : nullptr;
         make_desc(&d[a], get64(r), ptr, get64(r + 8), get64(r + 16), kNoChunk, C);
     }
-    const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
+    const bool per_alloc = (o && (o->flags & CKPT_OPT_PER_ALLOC)) || some;
     int T, K;
     pick_tile(C, o ? o->wg_threads : 0, &T, &K);
     uint64_t slot;
     int nslots;
     pick_staging(c, o, nc, C, &slot, &nslots);
-    std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
+    std::vector<Window> wins;
+    if (some) {
+        // windows over the selected allocations' chunks only
+        std::vector<AllocDesc> chosen;
+        for (uint64_t a = 0; a < v.n_allocs; ++a)
+            if (sel[a] >= 0) chosen.push_back(d[a]);
+        wins = plan_windows(chosen, nc, C, slot, true);
+    } else {
+        wins = plan_windows(d, nc, C, slot, per_alloc);
+    }
     const uint64_t W = wins.size();
     const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
 
@@ -1110,7 +1138,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
                    ctl_wtk = ctl_err + 8;
     HIPCHK(c->ctl.ensure(ctl_wtk + 4 * (W + 2) + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 2) + 128));
-    HIPCHK(ensure_events(c, 2 * W + (size_t)nslots + 2));
+    HIPCHK(ensure_events(c, std::max<size_t>(2 * W + (size_t)nslots + 2, ncs)));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
     if (timing) HIPCHK(ensure_tevents(c, 2 * W));
     const EngineConsts* ec;
@@ -1171,39 +1199,56 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     if (crc_combine(hdig[0], hdig[1], len_b) != v.tables_crc) return CKPT_ECORRUPT;
     const uint64_t nz = hq[0], nd = hq[1], nu = hq[2], ninv = hq[3];
     if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != nc) return CKPT_ECORRUPT;
-    // window offsets: payload total must equal D
-    std::vector<uint64_t> wbh;
+    // window payload ranges [wbeg, wend); the payload total must equal D
+    std::vector<uint64_t> wbeg(W), wend(W);
     if (nc) {
         if (per_alloc) {
-            wbh.assign(W + 1, 0);
-            uint64_t acc = 0, w = 0;
+            // per-allocation (or selected-allocation) windows: from a host
+            // prefix over the payload lengths
+            std::vector<uint64_t> pre(nc + 1, 0);
             for (uint64_t a = 0; a < v.n_allocs; ++a) {
                 const uint64_t nk = ceil_div(d[a].size, C);
                 for (uint64_t k = 0; k < nk; ++k) {
                     const uint64_t gg = d[a].first + k;
-                    while (w < W && wins[w].g0 == gg) wbh[w++] = acc;
-                    if (v.kinds[gg] == kData) acc += round16(k + 1 == nk ? d[a].tail_len : C);
+                    pre[gg + 1] = pre[gg] + (v.kinds[gg] == kData ? round16(k + 1 == nk ? d[a].tail_len : C) : 0);
                 }
             }
-            wbh[W] = acc;
+            if (pre[nc] != v.D) return CKPT_ECORRUPT;
+            for (uint64_t w = 0; w < W; ++w) {
+                wbeg[w] = pre[wins[w].g0];
+                wend[w] = pre[wins[w].g1];
+            }
         } else {
             HIPCHK(hipMemcpy(hwb, c->wb.p, 8 * (W + 1), hipMemcpyDeviceToHost));
-            wbh.assign(hwb, hwb + W + 1);
+            if (hwb[W] != v.D) return CKPT_ECORRUPT;
+            for (uint64_t w = 0; w < W; ++w) {
+                wbeg[w] = hwb[w];
+                wend[w] = hwb[w + 1];
+            }
         }
-        if (wbh[W] != v.D) return CKPT_ECORRUPT;
     } else if (v.D != 0) {
         return CKPT_ECORRUPT;
     }
-    if (v.n_allocs != n) return CKPT_EMISMATCH;
-    for (uint32_t a = 0; a < n; ++a)
-        if (table->v[a].id != d[a].id || table->v[a].size != d[a].size) return CKPT_EMISMATCH;
+    if (some) {
+        uint32_t matched = 0;
+        for (uint64_t a = 0; a < v.n_allocs; ++a) {
+            if (sel[a] < 0) continue;
+            if (table->v[sel[a]].size != d[a].size) return CKPT_EMISMATCH;
+            ++matched;
+        }
+        if (matched != n) return CKPT_EMISMATCH;   // an id the image does not hold
+    } else {
+        if (v.n_allocs != n) return CKPT_EMISMATCH;
+        for (uint32_t a = 0; a < n; ++a)
+            if (table->v[a].id != d[a].id || table->v[a].size != d[a].size) return CKPT_EMISMATCH;
+    }
 
     // 2) a delta needs its base in place
     if (nu) {
         ChunkJob j;
         memset(&j, 0, sizeof(j));
         j.allocs = c->descs.as<AllocDesc>();
-        j.n_allocs = n;
+        j.n_allocs = (uint32_t)v.n_allocs;
         j.C = C;
         j.amap = c->amap.as<uint32_t>();
         j.g0 = 0;
@@ -1214,8 +1259,30 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         j.bad = bad;
         j.err = err;
         int grid;
-        HIPCHK(grid_for(c, T, K, kModeVerify, nc, &grid));
-        HIPCHK(launch_chunks(T, K, kModeVerify, one_job(j, wtk + W), grid, c->s_main));
+        if (!some) {
+            HIPCHK(grid_for(c, T, K, kModeVerify, nc, &grid));
+            HIPCHK(launch_chunks(T, K, kModeVerify, one_job(j, wtk + W), grid, c->s_main));
+        } else {
+            // only the chunks being restored, up to kMaxJobs windows per launch
+            for (uint64_t w0 = 0; w0 < W; w0 += kMaxJobs) {
+                JobList jl;
+                memset(&jl, 0, sizeof(jl));
+                uint64_t tot = 0;
+                for (uint64_t w = w0; w < std::min<uint64_t>(W, w0 + kMaxJobs); ++w) {
+                    jl.job[jl.n_jobs] = j;
+                    jl.job[jl.n_jobs].g0 = wins[w].g0;
+                    jl.job[jl.n_jobs].g1 = wins[w].g1;
+                    jl.prefix[jl.n_jobs] = tot;
+                    tot += wins[w].g1 - wins[w].g0;
+                    jl.n_jobs++;
+                }
+                jl.prefix[jl.n_jobs] = tot;
+                jl.ticket = wtk + W;
+                HIPCHK(launch_fill32(wtk + W, 0, 1, c->s_main));
+                HIPCHK(grid_for(c, T, K, kModeVerify, tot, &grid));
+                HIPCHK(launch_chunks(T, K, kModeVerify, jl, grid, c->s_main));
+            }
+        }
         HIPCHK(hipMemcpyAsync(hq + 4, bad, 8, hipMemcpyDeviceToHost, c->s_main));
         HIPCHK(hipStreamSynchronize(c->s_main));
         if (hq[4] != kNoChunk) {
@@ -1228,21 +1295,81 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     std::vector<hipEvent_t>& ev = c->events;   // [0,W): copied; [W, W+nslots): slot free
     std::vector<bool> slot_used(nslots, false);
     const uint64_t t_link0 = now_ns();
-    for (uint64_t w = 0; w < W; ++w) {
+    uint64_t moved_all = 0;
+    for (uint64_t w = 0; w < W; ++w) moved_all += wend[w] - wbeg[w];
+    // On-demand restore whose payload fits the staging: the listed
+    // allocations' records go up in one copy per contiguous payload run (on
+    // the copy streams in turn), then the windows are restored by launches of
+    // up to kMaxJobs windows each.
+    const bool merged = some && W > 0 && moved_all <= (uint64_t)nslots * slot;
+    if (merged) {
+        std::vector<uint64_t> sofs(W + 1, 0);
+        for (uint64_t w = 0; w < W; ++w) sofs[w + 1] = sofs[w] + (wend[w] - wbeg[w]);
+        uint64_t runs = 0;
+        for (uint64_t w = 0; w < W;) {
+            uint64_t e = w + 1;
+            while (e < W && wend[e - 1] == wbeg[e]) ++e;
+            const uint64_t len = wend[e - 1] - wbeg[w];
+            hipStream_t cs = c->s_copy[runs % ncs];
+            if (len)
+                HIPCHK(hipMemcpyAsync(c->staging.as<uint8_t>() + sofs[w], v.payload + wbeg[w], len,
+                                      hipMemcpyHostToDevice, cs));
+            ++runs;
+            w = e;
+        }
+        for (uint32_t i = 0; i < ncs && i < runs; ++i) {
+            HIPCHK(hipEventRecord(ev[i], c->s_copy[i]));
+            HIPCHK(hipStreamWaitEvent(c->s_main, ev[i], 0));
+        }
+        const uint64_t nl = ceil_div(W, (uint64_t)kMaxJobs);
+        for (uint64_t l = 0; l < nl; ++l) {
+            JobList jl;
+            memset(&jl, 0, sizeof(jl));
+            uint64_t tot = 0;
+            for (uint64_t w = l * kMaxJobs; w < std::min<uint64_t>(W, (l + 1) * kMaxJobs); ++w) {
+                ChunkJob& j = jl.job[jl.n_jobs];
+                j.allocs = c->descs.as<AllocDesc>();
+                j.n_allocs = (uint32_t)v.n_allocs;
+                j.C = C;
+                j.amap = c->amap.as<uint32_t>();
+                j.g0 = wins[w].g0;
+                j.g1 = wins[w].g1;
+                j.ec = ec;
+                j.kind_in = kind_dev;
+                j.ref_crc = crc_dev;
+                j.slot = c->staging.as<uint8_t>() + sofs[w];
+                j.off = c->off.as<uint64_t>();
+                j.slot_base = wbeg[w];
+                j.bad = bad;
+                j.err = err;
+                jl.prefix[jl.n_jobs] = tot;
+                tot += j.g1 - j.g0;
+                jl.n_jobs++;
+            }
+            jl.prefix[jl.n_jobs] = tot;
+            jl.ticket = wtk + l;
+            int grid;
+            HIPCHK(grid_for(c, T, K, kModeRestore, tot, &grid));
+            if (timing) HIPCHK(hipEventRecord(c->tevents[2 * l], c->s_main));
+            HIPCHK(launch_chunks(T, K, kModeRestore, jl, grid, c->s_main));
+            if (timing) HIPCHK(hipEventRecord(c->tevents[2 * l + 1], c->s_main));
+        }
+    }
+    for (uint64_t w = 0; w < W && !merged; ++w) {
         const int s = (int)(w % nslots);
         hipStream_t cs = c->s_copy[w % ncs];
         uint8_t* sp = c->staging.as<uint8_t>() + (uint64_t)s * slot;
         if (slot_used[s]) HIPCHK(hipStreamWaitEvent(cs, ev[W + s], 0));
         slot_used[s] = true;
-        const uint64_t len = wbh[w + 1] - wbh[w];
+        const uint64_t len = wend[w] - wbeg[w];
         if (len > slot) return CKPT_ECORRUPT;
-        if (len) HIPCHK(hipMemcpyAsync(sp, v.payload + wbh[w], len, hipMemcpyHostToDevice, cs));
+        if (len) HIPCHK(hipMemcpyAsync(sp, v.payload + wbeg[w], len, hipMemcpyHostToDevice, cs));
         HIPCHK(hipEventRecord(ev[w], cs));
         HIPCHK(hipStreamWaitEvent(c->s_main, ev[w], 0));
         ChunkJob j;
         memset(&j, 0, sizeof(j));
         j.allocs = c->descs.as<AllocDesc>();
-        j.n_allocs = n;
+        j.n_allocs = (uint32_t)v.n_allocs;
         j.C = C;
         j.amap = c->amap.as<uint32_t>();
         j.g0 = wins[w].g0;
@@ -1252,7 +1379,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         j.ref_crc = crc_dev;
         j.slot = sp;
         j.off = c->off.as<uint64_t>();
-        j.slot_base = wbh[w];
+        j.slot_base = wbeg[w];
         j.bad = bad;
         j.err = err;
         int grid;
@@ -1266,7 +1393,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     CombineJob cj;
     memset(&cj, 0, sizeof(cj));
     cj.allocs = c->descs.as<AllocDesc>();
-    cj.n_allocs = n;
+    cj.n_allocs = (uint32_t)v.n_allocs;
     cj.C = C;
     cj.crc = crc_dev;
     cj.ec = ec;
@@ -1283,16 +1410,20 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         return CKPT_EHIP;
     }
     if (res) {
+        uint64_t moved = 0, logical = 0;
+        for (uint64_t w = 0; w < W; ++w) moved += wend[w] - wbeg[w];
+        for (uint64_t a = 0; a < v.n_allocs; ++a)
+            if (sel[a] >= 0) logical += d[a].size;
         res->windows = (uint32_t)W;
-        res->n_logical = v.N;
-        res->n_payload = v.D;
+        res->n_logical = logical;
+        res->n_payload = moved;
         res->n_chunks = nc;
         res->n_zero = nz;
         res->n_data = nd;
         res->n_unchanged = nu;
-        res->link_bytes = v.D + tl + kHeader;
+        res->link_bytes = moved + tl + kHeader;
         res->ns_link = t_link1 - t_link0;
-        res->ns_kernel = timing ? timed_ns(c, W) : 0;
+        res->ns_kernel = timing ? timed_ns(c, merged ? ceil_div(W, (uint64_t)kMaxJobs) : W) : 0;
         res->ns_total = now_ns() - t_start;
     }
     if (hq[4] != kNoChunk) {
@@ -1311,7 +1442,15 @@ extern "C" int ckpt_restore(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc
     fill_result(res);
     if (!c || !img || !table) return CKPT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    return restore_impl(c, img, table, o, stream, res);
+    return restore_impl(c, img, table, o, stream, res, false);
+}
+
+extern "C" int ckpt_restore_some(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table,
+                                 const ckpt_opts* o, void* stream, ckpt_result* res) {
+    fill_result(res);
+    if (!c || !img || !table) return CKPT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    return restore_impl(c, img, table, o, stream, res, true);
 }
 
 // ------------------------------------------------------------ autotuner

@@ -100,6 +100,9 @@ def lib():
         L.ckpt_restore.argtypes = [vp, vp, ctypes.POINTER(ckpt_alloc_table), ctypes.POINTER(ckpt_opts), vp,
                                    ctypes.POINTER(ckpt_result)]
         L.ckpt_restore.restype = ctypes.c_int
+        L.ckpt_restore_some.argtypes = [vp, vp, ctypes.POINTER(ckpt_alloc_table), ctypes.POINTER(ckpt_opts), vp,
+                                   ctypes.POINTER(ckpt_result)]
+        L.ckpt_restore_some.restype = ctypes.c_int
         L.ckpt_merge.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.ckpt_merge.restype = ctypes.c_int
         L.ckpt_image_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(_u64)]
@@ -254,6 +257,15 @@ def ckpt_restore(ctx, image, table, opts=None, stream=None):
     res = ckpt_result()
     rc = lib().ckpt_restore(ctx, image.handle, ctypes.byref(tab),
                             ctypes.byref(opts) if opts is not None else None, _stream(stream), ctypes.byref(res))
+    return rc, res
+
+
+def ckpt_restore_some(ctx, image, table, opts=None, stream=None):
+    """On-demand restore of the listed allocations only (matched by id)."""
+    tab, keep = _table(table)
+    res = ckpt_result()
+    rc = lib().ckpt_restore_some(ctx, image.handle, ctypes.byref(tab),
+                                 ctypes.byref(opts) if opts is not None else None, _stream(stream), ctypes.byref(res))
     return rc, res
 
 

@@ -273,3 +273,55 @@ def test_pageable_host_images(ctx):
         check_parity(ctx, table, c, window_bytes=2 * c)
     finally:
         del os.environ["MICKPT_HOST_PAGEABLE"]
+
+
+def test_on_demand_restore_of_listed_allocations(ctx):
+    """ckpt_restore_some: the listed allocations (any order, by id) get the
+    bytes the oracle restores from the same image; unlisted targets are not
+    touched; unknown ids, other sizes and repeated ids are rejected."""
+    c = 65536
+    rng = np.random.default_rng(33)
+    gen = torch.Generator(device=DEV).manual_seed(33)
+    table = _rand_table(rng, gen, 14, c, max_chunks=10)
+    img, oimg, _ = check_parity(ctx, table, c)
+    # the oracle's restore of the whole image: the reference bytes
+    ref = [(i, np.zeros(t.numel(), np.uint8)) for i, t in table]
+    rc, first_bad = corc.restore(oimg, ref)
+    assert rc == 0
+    targets = [(i, torch.full_like(t, 0xA5) if t.numel() else t.clone()) for i, t in table]
+    pick = [5, 0, 11, 3, 8]                      # any order
+    for opts in (None, mk.make_opts(window_bytes=2 * c)):
+        for _, t in targets:
+            t.fill_(0xA5)
+        rc, res = mk.ckpt_restore_some(ctx, img, [targets[k] for k in pick], opts=opts)
+        assert rc == 0, mk.ckpt_strerror(rc)
+        torch.cuda.synchronize()
+        for k, ((_, t), (_, r)) in enumerate(zip(targets, ref)):
+            got = t.cpu().numpy()
+            if k in pick:
+                assert np.array_equal(got, r), k
+            else:
+                assert (got == 0xA5).all(), k         # untouched
+        assert res.n_logical == sum(table[k][1].numel() for k in pick)
+    # the remaining allocations in a second call complete the restore
+    rest = [targets[k] for k in range(len(table)) if k not in pick]
+    assert mk.ckpt_restore_some(ctx, img, rest)[0] == 0
+    torch.cuda.synchronize()
+    for (_, t), (_, r) in zip(targets, ref):
+        assert np.array_equal(t.cpu().numpy(), r)
+    # errors
+    big = [k for k, (_, t) in enumerate(table) if t.numel() > 0][0]
+    wrong_size = [(table[big][0], torch.zeros(table[big][1].numel() + 16, dtype=torch.uint8, device=DEV))]
+    assert mk.ckpt_restore_some(ctx, img, wrong_size)[0] == mk.CKPT_EMISMATCH
+    assert mk.ckpt_restore_some(ctx, img, [(12345, targets[0][1])])[0] == mk.CKPT_EMISMATCH
+    assert mk.ckpt_restore_some(ctx, img, [targets[big], targets[big]])[0] == mk.CKPT_EINVAL
+    # a delta: the listed allocations must hold the base in their UNCHANGED chunks
+    new = [(i, t.clone()) for i, t in table]
+    workloads.mutate_runs(new, seed=34, chunk=c, frac=0.3, run_mean=2)
+    d_img, _, dres = check_parity(ctx, new, c, prev_gpu=img, prev_oracle=oimg)
+    assert dres.n_unchanged > 0
+    base_targets = [(i, t.clone()) for i, t in table]
+    assert mk.ckpt_restore_some(ctx, d_img, [base_targets[k] for k in pick])[0] == 0
+    torch.cuda.synchronize()
+    for k in pick:
+        assert torch.equal(base_targets[k][1], new[k][1])
