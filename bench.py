@@ -57,14 +57,27 @@ def link_baseline(torch, nbytes=4 << 30, reps=3):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dump_kernel_traffic_training.json")
 KERNEL_SOURCES = ("paper_2502_16631_amd/csrc/kernels.hip", "paper_2502_16631_amd/csrc/kernels.h",
-                  "paper_2502_16631_amd/csrc/common.h", "paper_2502_16631_amd/build.sh")
+                  "paper_2502_16631_amd/csrc/common.h")
+BUILD_SCRIPT = "paper_2502_16631_amd/build.sh"
 
 
 def kernel_source_hash():
+    """SHA-256 over the kernel sources and the kernels' compile flags (the
+    FLAGS / KFLAGS arrays of the build script)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    flags, inside = [], False
+    with open(os.path.join(ROOT, BUILD_SCRIPT)) as fh:
+        for line in fh:
+            if line.startswith(("FLAGS=(", "KFLAGS=(")):
+                inside = True
+            if inside:
+                flags.append(line)
+                if line.rstrip().endswith(")"):
+                    inside = False
+    h.update("".join(flags).encode())
     return h.hexdigest()
 
 
@@ -150,11 +163,15 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--cpu-sample", type=float, default=16e9, help="bytes of the oracle sample (0 = skip); ~10-15 s of CPU work")
     ap.add_argument("--check", action="store_true", help="verify restored bytes after each step")
-    ap.add_argument("--form", default="plain", choices=["plain", "incremental", "batched", "serve", "ondemand"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "incremental", "batched", "serve", "ondemand", "storage"],
                     help="plain: full dump + restore (default); incremental: 40 GB HPC image, delta dump and "
                          "base + delta restore; batched: 10,000 allocations, graph-captured single launch vs "
                          "per-allocation launches, autotuned; serve: multi-tenant Poisson trace, p50/p99; "
-                         "ondemand: parameters restored first vs one full restore")
+                         "ondemand: parameters restored first vs one full restore; "
+                         "storage: dump + image to file, file + restore")
+    ap.add_argument("--path", default="/tmp/mickpt_bench.img", help="storage: image file (removed afterwards)")
+    ap.add_argument("--io-threads", type=int, default=8, help="storage: file I/O threads")
     ap.add_argument("--scale", type=float, default=1.0, help="scale the total bytes of the non-plain forms")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: aggregate requests per second")
@@ -170,7 +187,8 @@ def main():
     if args.form != "plain":
         import bench_forms
         line = {"incremental": bench_forms.incremental, "batched": bench_forms.batched,
-                "serve": bench_forms.serve, "ondemand": bench_forms.ondemand}[args.form](
+                "serve": bench_forms.serve, "ondemand": bench_forms.ondemand,
+                "storage": bench_forms.storage}[args.form](
                     args, torch, mk, link_baseline(torch))
         print(json.dumps(line), flush=True)
         return

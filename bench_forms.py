@@ -326,3 +326,60 @@ def ondemand(args, torch, mk, link):
         "speedup_to_parameters": round(_pct(t_full, 50) / tp, 2),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
     }
+
+
+def storage(args, torch, mk, link):
+    """Storage leg on the training state (~27 GB): dump, then the image to a
+    file (synced); the file back into an image, then restore. Times each
+    part; the file is removed afterwards."""
+    import os
+    table = workloads.training_state("cuda", seed=2)
+    torch.cuda.synchronize()
+    N = _nbytes(table)
+    ctx = mk.ckpt_ctx_create(0, max(args.budget, N + (1 << 30)))
+    opts = mk.make_opts(chunk_size=C)
+    path = args.path
+    td, ts, tl, tr = [], [], [], []
+    size = 0
+    try:
+        for k in range(args.warmup + args.steps):
+            t0 = time.perf_counter()
+            rc, img, _ = mk.ckpt_dump(ctx, table, opts=opts)
+            t1 = time.perf_counter()
+            assert rc == 0
+            rc = mk.ckpt_image_save(img, path, args.io_threads)
+            t2 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            size = img.nbytes()
+            img.free()
+            rc, img2 = mk.ckpt_image_load(path, args.io_threads)
+            t3 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            rc, _ = mk.ckpt_restore(ctx, img2, table, opts=opts)
+            t4 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            img2.free()
+            if k >= args.warmup:
+                td.append(t1 - t0)
+                ts.append(t2 - t1)
+                tl.append(t3 - t2)
+                tr.append(t4 - t3)
+            _log("step %d: dump %.3f s, save %.3f s, load %.3f s, restore %.3f s" % (k, t1 - t0, t2 - t1, t3 - t2, t4 - t3))
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
+        mk.ckpt_ctx_destroy(ctx)
+    md = lambda xs: _pct(xs, 50)
+    dump_save = md(td) + md(ts)
+    load_restore = md(tl) + md(tr)
+    return {
+        "metric": "dump-to-file and restore-from-file GB/s at 1 GPU", "form": "storage",
+        "value": round(2 * N / (dump_save + load_restore) / 1e9, 3), "unit": "GB/s (logical, dump+save and load+restore)",
+        "config": {"workload": "decoder-1.3B training state (303 allocations)", "chunk": C, "N_bytes": N,
+                   "image_bytes": size, "io_threads": args.io_threads, "path": path},
+        "dump_ms_p50": round(md(td) * 1e3, 1), "save_ms_p50": round(md(ts) * 1e3, 1),
+        "load_ms_p50": round(md(tl) * 1e3, 1), "restore_ms_p50": round(md(tr) * 1e3, 1),
+        "dump_and_save_GBps": round(N / dump_save / 1e9, 3), "load_and_restore_GBps": round(N / load_restore / 1e9, 3),
+        "file_write_GBps": round(size / md(ts) / 1e9, 3), "file_read_GBps": round(size / md(tl) / 1e9, 3),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+    }

@@ -49,6 +49,7 @@ extern "C" {
 #define CKPT_EBASE     -6  /* delta without its base: restore target does not hold the base
                               state (first_bad_chunk set), or merge with the wrong base       */
 #define CKPT_ETIMEOUT  -7  /* serving: request deadline passed before completion            */
+#define CKPT_EIO       -8  /* a file could not be opened, written, synced or read            */
 
 /* chunk kinds stored in an image */
 #define CKPT_KIND_ZERO      0
@@ -179,6 +180,20 @@ int  ckpt_image_bytes(const ckpt_image* img, const void** p, uint64_t* n);
 int  ckpt_image_import(const void* p, uint64_t n, ckpt_image** out);
 /* Free an image. NULL is a no-op. */
 void ckpt_image_free(ckpt_image* img);
+
+/* Storage (section 3.2: the AMD GPU plugin saves the GPU state into
+ * checkpoint files; section 5.1 measures the memory write time to persistent
+ * storage, and section 5.2 finds restores bounded also by loading checkpoint
+ * data from disk). ckpt_image_save writes the image's bytes to `path`
+ * (created or truncated) with `threads` threads (0 = 8) of positional writes,
+ * O_DIRECT for the page-aligned prefix when the file system accepts it, and
+ * syncs the file before returning. ckpt_image_load reads such a file into a
+ * new image (pinned if available) and validates it like ckpt_image_import
+ * (CKPT_ECORRUPT on a bad header or tables digest; payload records are
+ * verified by the restore). Both return CKPT_EIO when the file cannot be
+ * opened, written, synced or read in full. */
+int  ckpt_image_save(const ckpt_image* img, const char* path, uint32_t threads);
+int  ckpt_image_load(const char* path, uint32_t threads, ckpt_image** out);
 /* Static description of an error code. */
 const char* ckpt_strerror(int code);
 /* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes. */

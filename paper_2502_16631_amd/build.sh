@@ -19,8 +19,10 @@ hipcc "${FLAGS[@]}" -c "$SRC/serve.hip" -o "$BUILD/serve.o" &
 p4=$!
 hipcc -O2 -std=c++17 -fPIC -Wall -c "$SRC/hostmath.cpp" -o "$BUILD/hostmath.o" &
 p3=$!
-wait $p1; wait $p2; wait $p3; wait $p4
+g++ -O2 -std=c++17 -fPIC -Wall -D__HIP_PLATFORM_AMD__ -I/opt/rocm/include -c "$SRC/storage.cpp" -o "$BUILD/storage.o" &
+p5=$!
+wait $p1; wait $p2; wait $p3; wait $p4; wait $p5
 hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/serve.o" \
-    "$BUILD/hostmath.o" -lpthread
+    "$BUILD/hostmath.o" "$BUILD/storage.o" -lpthread
 mv "$OUT.tmp" "$OUT"
 echo "built $OUT"

@@ -57,7 +57,7 @@ struct DevBuf {
         return hipSuccess;
     }
     void release() {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         cap = 0;
     }

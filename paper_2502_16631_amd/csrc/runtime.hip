@@ -1659,6 +1659,7 @@ extern "C" const char* ckpt_strerror(int code) {
         case CKPT_EMISMATCH: return "allocation table does not match the image";
         case CKPT_EBASE: return "delta image without its base";
         case CKPT_ETIMEOUT: return "deadline passed";
+        case CKPT_EIO: return "file input/output failed";
         default: return "unknown error";
     }
 }

@@ -28,6 +28,7 @@ CKPT_ECORRUPT = -4
 CKPT_EMISMATCH = -5
 CKPT_EBASE = -6
 CKPT_ETIMEOUT = -7
+CKPT_EIO = -8
 KIND_ZERO, KIND_DATA, KIND_UNCHANGED = 0, 1, 2
 OPT_PER_ALLOC = 1
 OPT_GRAPH = 2
@@ -103,6 +104,10 @@ def lib():
         L.ckpt_restore_some.argtypes = [vp, vp, ctypes.POINTER(ckpt_alloc_table), ctypes.POINTER(ckpt_opts), vp,
                                    ctypes.POINTER(ckpt_result)]
         L.ckpt_restore_some.restype = ctypes.c_int
+        L.ckpt_image_save.argtypes = [vp, ctypes.c_char_p, _u32]
+        L.ckpt_image_save.restype = ctypes.c_int
+        L.ckpt_image_load.argtypes = [ctypes.c_char_p, _u32, ctypes.POINTER(vp)]
+        L.ckpt_image_load.restype = ctypes.c_int
         L.ckpt_merge.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.ckpt_merge.restype = ctypes.c_int
         L.ckpt_image_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(_u64)]
@@ -276,6 +281,18 @@ def ckpt_autotune(ctx, table, sample_bytes=0, flags=0):
     rc = lib().ckpt_autotune(ctx, ctypes.byref(tab), int(sample_bytes), int(flags), ctypes.byref(best),
                              ctypes.byref(gbps))
     return rc, best, gbps.value
+
+
+def ckpt_image_save(image, path, threads=0):
+    """Write the image to a file (synced)."""
+    return lib().ckpt_image_save(image.handle, os.fsencode(path), int(threads))
+
+
+def ckpt_image_load(path, threads=0):
+    """Read and validate an image file: (rc, Image or None)."""
+    out = ctypes.c_void_p()
+    rc = lib().ckpt_image_load(os.fsencode(path), int(threads), ctypes.byref(out))
+    return rc, (Image(out.value) if rc == 0 else None)
 
 
 def ckpt_merge(base, delta):

@@ -325,3 +325,18 @@ def test_on_demand_restore_of_listed_allocations(ctx):
     torch.cuda.synchronize()
     for k in pick:
         assert torch.equal(base_targets[k][1], new[k][1])
+
+
+def test_image_file_round_trip(ctx, tmp_path):
+    """A dumped image (pinned host memory) saved to a file and loaded back is
+    byte-identical and restores the state."""
+    c = 65536
+    rng = np.random.default_rng(35)
+    gen = torch.Generator(device=DEV).manual_seed(35)
+    table = _rand_table(rng, gen, 10, c, max_chunks=200)
+    img, oimg, _ = check_parity(ctx, table, c)
+    path = str(tmp_path / "state.img")
+    assert mk.ckpt_image_save(img, path, 4) == 0
+    rc, back = mk.ckpt_image_load(path, 3)
+    assert rc == 0 and np.array_equal(back.view(), oimg)
+    restore_and_compare(ctx, back, table)

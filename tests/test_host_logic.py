@@ -89,3 +89,54 @@ def test_combine_reproduces_whole_allocation_crc(emu):
                 assert emu.emu_alloc_crc(crcs.ctypes.data, size, c, threads) == hw_crc32c(data)
     a, b = b"hello ", b"world"
     assert emu.emu_combine(hw_crc32c(a), hw_crc32c(b), len(b)) == hw_crc32c(a + b)
+
+
+def test_image_save_load_round_trip(mklib, tmp_path):
+    """Image files: save writes exactly the image's bytes, load reads them
+    back and validates them; corrupt, truncated and missing files are
+    rejected. Images come from the CPU oracle (on a machine without a GPU the
+    library keeps them in pageable memory). Sizes cross several 64 MiB I/O
+    pieces and leave an unaligned tail."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as corc
+    rng = np.random.default_rng(5)
+    sizes = [0, 1, 5000, 65536, 70_000_001, 80 << 20]
+    allocs = [(i + 1, rng.integers(0, 256, size=s, dtype=np.uint8)) for i, s in enumerate(sizes)]
+    allocs[3][1][:] = 0
+    rc, img = corc.dump(allocs, 65536)
+    assert rc == 0 and img.size > (128 << 20) and img.size % 4096
+    vp = ctypes.c_void_p
+    mklib.ckpt_image_import.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+    mklib.ckpt_image_save.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32]
+    mklib.ckpt_image_load.argtypes = [ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(vp)]
+    mklib.ckpt_image_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]
+    mklib.ckpt_image_free.argtypes = [vp]
+    h = vp()
+    assert mklib.ckpt_image_import(img.ctypes.data, img.size, ctypes.byref(h)) == 0
+    path = str(tmp_path / "state.img").encode()
+    assert mklib.ckpt_image_save(h, path, 3) == 0
+    with open(path, "rb") as f:
+        assert f.read() == img.tobytes()
+    h2 = vp()
+    assert mklib.ckpt_image_load(path, 2, ctypes.byref(h2)) == 0
+    p, n = vp(), ctypes.c_uint64()
+    assert mklib.ckpt_image_bytes(h2, ctypes.byref(p), ctypes.byref(n)) == 0
+    assert ctypes.string_at(p.value, n.value) == img.tobytes()
+    mklib.ckpt_image_free(h2)
+    # a flipped header byte, a flipped tables byte, a truncated file, no file
+    raw = bytearray(img.tobytes())
+    for pos in (20, 64 + 3):
+        bad = bytearray(raw)
+        bad[pos] ^= 0x40
+        with open(path, "wb") as f:
+            f.write(bad)
+        h3 = vp()
+        assert mklib.ckpt_image_load(path, 4, ctypes.byref(h3)) == -4 and not h3.value
+    with open(path, "wb") as f:
+        f.write(raw[:len(raw) // 2])
+    h3 = vp()
+    assert mklib.ckpt_image_load(path, 4, ctypes.byref(h3)) == -4
+    assert mklib.ckpt_image_load(str(tmp_path / "missing.img").encode(), 4, ctypes.byref(h3)) == -8
+    assert mklib.ckpt_image_save(h, str(tmp_path / "no" / "dir.img").encode(), 2) == -8
+    mklib.ckpt_image_free(h)
