@@ -43,7 +43,7 @@ def lib():
         L.orc_image_bound.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_uint32]
         L.orc_dump.restype = ctypes.c_int
         L.orc_dump.argtypes = [ctypes.c_uint32, _u64p, _u64p, ctypes.POINTER(_u8p), ctypes.c_uint32,
-                               _u8p, ctypes.c_uint64, ctypes.c_int, _u8p, ctypes.c_uint64, _u64p]
+                               ctypes.c_int, _u8p, ctypes.c_uint64, ctypes.c_int, _u8p, ctypes.c_uint64, _u64p]
         L.orc_restore.restype = ctypes.c_int
         L.orc_restore.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, _u64p, _u64p,
                                   ctypes.POINTER(_u8p), ctypes.c_int, _u64p]
@@ -91,8 +91,9 @@ def _table(allocs):
     return n, ids, sizes, ptrs, keep
 
 
-def dump(allocs, c, prev=None, threads=None):
-    """allocs: list of (id, array) in table order. Returns (rc, image array or None)."""
+def dump(allocs, c, prev=None, threads=None, codec=False):
+    """allocs: list of (id, array) in table order. Returns (rc, image array or None).
+    codec: store full DATA chunks as byte-plane records where shorter."""
     n, ids, sizes, ptrs, keep = _table(allocs)
     cap = 80
     if n:
@@ -105,7 +106,7 @@ def dump(allocs, c, prev=None, threads=None):
         plen = pv.size
     else:
         pp, plen = None, 0
-    rc = lib().orc_dump(n, ids.ctypes.data_as(_u64p), sizes.ctypes.data_as(_u64p), ptrs, c,
+    rc = lib().orc_dump(n, ids.ctypes.data_as(_u64p), sizes.ctypes.data_as(_u64p), ptrs, c, int(bool(codec)),
                         pp, plen, threads or default_threads(),
                         out.ctypes.data_as(_u8p), out.size, ctypes.byref(olen))
     if rc != 0:
