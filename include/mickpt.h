@@ -77,11 +77,26 @@ typedef struct ckpt_ctx ckpt_ctx;       /* device context: staging, streams, dig
 typedef struct ckpt_image ckpt_image;   /* an image in host memory (pinned if available)  */
 
 /* Tuning knobs. None of them changes the bytes of an image except
- * chunk_size, which is recorded in its header. Pass NULL for defaults. */
+ * chunk_size, which is recorded in its header, and CKPT_OPT_CODEC. Pass NULL
+ * for defaults. */
 #define CKPT_OPT_PER_ALLOC  1u   /* launch the kernels once per allocation (baseline form)   */
 #define CKPT_OPT_GRAPH      2u   /* batched form: capture the device stage in a hipGraph and
                                     replay it (cached per table shape)                      */
 #define CKPT_OPT_NO_TIMING  4u   /* skip per-stage device timing events                      */
+/* Dump only (ignored by restore, where the image says how it is stored):
+ * store each full-length DATA chunk as a byte-plane record when that record
+ * is shorter (kind PACKED = 3; the image gets header flag bit 1 and a u32
+ * record-length table between the digest and kind tables). The paper names
+ * data compression as a way to speed up checkpoint and restore of large
+ * models (section 5.2) and among the optimisations its method can take on
+ * (section 7); the codec is this library's: 8 byte planes per chunk, each
+ * stored as one value, as 4-bit codes into a 15-entry dictionary of its most
+ * frequent bytes plus escaped bytes, or raw. It needs 4096 <= chunk_size <=
+ * 65536, no CKPT_OPT_PER_ALLOC or CKPT_OPT_GRAPH (CKPT_EINVAL otherwise),
+ * and a staging budget that holds the whole payload in one window
+ * (CKPT_ENOMEM otherwise). Restoring PACKED records needs the same chunk
+ * sizes (CKPT_EINVAL otherwise). */
+#define CKPT_OPT_CODEC      8u
 typedef struct {
     uint32_t chunk_size;     /* bytes per chunk; 0 = 65536                                   */
     uint32_t wg_threads;     /* work-group size of the chunk kernels; 0 = chosen per size   */
@@ -105,7 +120,8 @@ typedef struct {
     uint64_t ns_total;          /* wall time of the call                                    */
     uint64_t ns_kernel;         /* summed device time of the chunk kernels                  */
     uint64_t ns_link;           /* wall time from first to last host-link copy              */
-    uint64_t reserved[4];
+    uint64_t n_packed;          /* PACKED chunks (codec records; not counted in n_data)     */
+    uint64_t reserved[3];
 } ckpt_result;
 
 /* ------------------------------------------------------------------ context */

@@ -1,0 +1,69 @@
+// Byte-plane codec of full-length DATA chunks (kind kPacked), gfx950.
+//
+// The paper names data compression among the techniques that could speed up
+// checkpoint and restore of large models (section 5.2) and among the
+// optimisations its method can take on (section 7); it defines no codec.
+// This one targets what a device's memory holds in training and HPC jobs:
+// arrays of 2-, 4- and 8-byte numbers whose high (sign / exponent) bytes take
+// few values. A chunk of C bytes is read as 8 byte planes (plane p = bytes
+// p, p+8, p+16, ...; element e of plane p is byte 8e+p); each plane is stored
+//   CONST  one value (16-byte section),
+//   DICT   a 15-entry dictionary of its most frequent bytes (count
+//          descending, value ascending), 4-bit codes (15 = escape, low
+//          nibble first) and the escaped bytes in element order,
+//   RAW    its bytes,
+// in 16-byte-aligned sections after a 48-byte head (u8 mode[8], u32 esc[8],
+// 8 zero bytes). DICT is chosen when its section is shorter than RAW; the
+// record replaces the chunk only when it is shorter than C. The image then
+// carries a u32 record-length table after the digest table.
+//
+// Work-group shape: 256 threads; lane t owns the C/4096 consecutive 16-byte
+// rows starting at row t*C/4096, so its elements of every plane are
+// consecutive and one block scan gives every lane its escape positions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace mk {
+
+constexpr uint32_t kCodecMinChunk = 4096;    // one 16-byte row per lane
+constexpr uint32_t kCodecMaxChunk = 65536;   // records are staged in LDS
+constexpr int kCodecThreads = 256;
+constexpr uint32_t kRecordHead = 48;
+enum : uint32_t { kPlaneRaw = 0, kPlaneConst = 1, kPlaneDict = 2 };
+
+inline bool codec_chunk_supported(uint32_t C) { return C >= kCodecMinChunk && C <= kCodecMaxChunk; }
+
+// Constants of the decode kernel's digest for one chunk size.
+struct CodecConsts {
+    uint32_t table[256];   // r(byte b): raw CRC of one byte (one lookup per byte)
+    uint32_t lane[256];    // x^(8 (C/256) (255 - t)): moves lane t's segment digest
+                           // to its place in the chunk
+    uint32_t full_init;    // (~0) * x^(8C): the preset's term
+    uint32_t pad[63];
+};
+void build_codec_consts(CodecConsts* cc, uint32_t C);
+
+// Size and encode passes over the chunks [0, n_chunks) of one table.
+struct PackJob {
+    const AllocDesc* allocs;
+    const uint32_t* amap;    // allocation of chunk g (required)
+    uint64_t n_chunks;
+    uint32_t C;
+    uint32_t pad;
+    uint8_t* kind;           // size: DATA becomes PACKED where the record is shorter
+    uint32_t* rlen;          // size: record length of every chunk (written); encode: read
+    const uint64_t* off;     // encode: payload offset of chunk g in slot
+    uint8_t* slot;           // encode: the payload (offset 0)
+    uint32_t* err;           // encode: set when a record's length differs from the size pass
+};
+
+// encode = false: size pass; true: encode pass (PACKED chunks to slot + off[g]).
+hipError_t launch_pack(const PackJob& j, bool encode, int grid, hipStream_t s);
+// Decode, store and verify the PACKED chunks of the jobs' ranges (restore):
+// uses allocs, amap, g0/g1, kind_in, ref_crc, slot, off, slot_base and bad of
+// each job; rlen is the image's record-length table (global chunk index).
+hipError_t launch_unpack(const JobList& jl, const uint32_t* rlen, const CodecConsts* cc, int grid, hipStream_t s);
+
+}  // namespace mk

@@ -30,7 +30,7 @@ constexpr uint32_t kPoly = 0x82F63B78u;   // P without the x^32 term, reflected
 constexpr uint32_t kOne = 0x80000000u;    // the polynomial 1
 constexpr uint32_t kX1 = 0x40000000u;     // the polynomial x
 
-enum : uint8_t { kZero = 0, kData = 1, kUnchanged = 2 };
+enum : uint8_t { kZero = 0, kData = 1, kUnchanged = 2, kPacked = 3 };   // kPacked: byte-plane record
 
 // b * x mod P
 __host__ __device__ inline uint32_t gf_xtimes(uint32_t b) {

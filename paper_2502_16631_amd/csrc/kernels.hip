@@ -27,7 +27,7 @@
 //             restore checks that the target holds the base);
 //   restore - DATA chunks read from the staging window, stored to their
 //             allocation and verified on the data in registers; ZERO chunks
-//             zero-filled.
+//             zero-filled (PACKED chunks are left to the codec's decode).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -350,7 +350,8 @@ k_chunks(JobList jl) {
         if constexpr (MODE == kModeVerify || MODE == kModeRestore || MODE == kModeGather) {
             kd_in = job.kind_in[g];
             if (MODE == kModeVerify && kd_in != kUnchanged) continue;
-            if (MODE == kModeRestore && kd_in == kUnchanged) continue;
+            // UNCHANGED: nothing to write; PACKED: the codec's decode kernel
+            if (MODE == kModeRestore && (kd_in == kUnchanged || kd_in == kPacked)) continue;
             if (MODE == kModeGather && kd_in != kData) continue;
         }
         const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);

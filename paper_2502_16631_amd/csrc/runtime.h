@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/mickpt.h"
+#include "codec.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -20,18 +21,24 @@ namespace mk {
 
 // Fields of an image in host memory (format v1), after checking the header
 // digest, the sizes and the allocation grid. With check_tables the tables
-// digest, the kinds and the payload length are checked as well and
-// state_digest is filled in.
+// digest, the kinds (and record lengths of the codec layout) and the payload
+// length are checked as well and state_digest is filled in.
 struct ImageView {
     uint32_t flags = 0, C = 0, n_allocs = 0, base_state = 0, tables_crc = 0, state_digest = 0;
     uint64_t n_chunks = 0, D = 0, N = 0, tl = 0;
     const uint8_t* recs = nullptr;
     const uint8_t* crcs = nullptr;
+    const uint8_t* rlens = nullptr;   // u32 record lengths (codec layout), else nullptr
     const uint8_t* kinds = nullptr;
     const uint8_t* payload = nullptr;
 };
 
 int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_tables);
+// Payload record length of chunk g (len = its length in bytes): 0 for ZERO
+// and UNCHANGED, round16(len) for DATA, the table's value for PACKED; or
+// kBadRecord when the kind or the record length breaks the format.
+constexpr uint64_t kBadRecord = ~0ull;
+uint64_t record_len(const ImageView& v, uint64_t g, uint64_t len);
 
 
 
@@ -91,7 +98,10 @@ uint64_t now_ns();
 inline uint64_t round16(uint64_t n) { return (n + 15) & ~15ull; }
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline bool valid_chunk(uint64_t c) { return c >= 16 && c <= (1ull << 30) && (c & (c - 1)) == 0; }
-inline uint64_t tables_len(uint64_t n, uint64_t nc) { return round16(32 * n + 5 * nc); }
+inline uint64_t tables_len(uint64_t n, uint64_t nc, bool codec = false) {
+    return round16(32 * n + (codec ? 9 : 5) * nc);
+}
+constexpr uint32_t kFlagDelta = 1, kFlagCodec = 2;
 inline void put32(uint8_t* p, uint32_t v) { memcpy(p, &v, 4); }
 inline void put64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
 inline uint32_t get32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
@@ -120,8 +130,9 @@ struct ckpt_ctx {
     uint32_t epoch = 0;
     uint64_t use_clock = 0;
     // device buffers
-    mk::DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig, amap;
+    mk::DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig, amap, rlen;
     std::map<std::pair<int, uint32_t>, mk::DevBuf> consts;    // (T, C) -> EngineConsts
+    std::map<uint32_t, mk::DevBuf> cconsts;                   // C -> CodecConsts
     std::map<std::tuple<int, int, int>, int> occ;          // (T, K, mode) -> blocks per CU
     std::unordered_map<uint64_t, mk::DigestEntry> digests;    // image uid -> resident crc[]
     std::vector<mk::GraphEntry> graphs;                       // captured dump stages (LRU)
@@ -140,6 +151,8 @@ void image_release(ckpt_image* im);   // returns the memory (pool or heap) and d
 uint32_t next_epoch(ckpt_ctx* c, bool* wrapped);
 void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K);
 hipError_t get_consts(ckpt_ctx* c, int T, uint32_t C, const EngineConsts** out);
+hipError_t get_codec_consts(ckpt_ctx* c, uint32_t C, const CodecConsts** out);
+int unpack_grid(const ckpt_ctx* c, uint64_t chunks);
 hipError_t grid_for(ckpt_ctx* c, int T, int K, int mode, uint64_t work, int* grid);
 void make_desc(AllocDesc* d, uint64_t id, const void* ptr, uint64_t size, uint64_t first, uint64_t prev_first,
                uint32_t C);

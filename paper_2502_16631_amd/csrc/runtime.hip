@@ -144,6 +144,20 @@ void mk::image_release(ckpt_image* im) {
 // ------------------------------------------------------------ parsed image
 namespace mk {
 
+uint64_t record_len(const ImageView& v, uint64_t g, uint64_t len) {
+    const uint8_t kd = v.kinds[g];
+    const bool delta = v.flags & kFlagDelta;
+    if (kd > kPacked || (kd == kUnchanged && !delta) || (kd == kPacked && !v.rlens)) return kBadRecord;
+    uint64_t want = kd == kData ? round16(len) : 0;
+    if (kd == kPacked) {
+        // a full chunk whose record (head + 8 sections of >= 16 bytes) is shorter
+        want = get32(v.rlens + 4 * g);
+        if (len != v.C || (want & 15) || want < kRecordHead + 8 * 16 || want >= v.C) return kBadRecord;
+    }
+    if (v.rlens && get32(v.rlens + 4 * g) != want) return kBadRecord;
+    return want;
+}
+
 int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_tables) {
     if (len < kHeader || memcmp(img, "MICKPT01", 8) != 0) return CKPT_ECORRUPT;
     if (host_crc32c(img, 60) != get32(img + 60)) return CKPT_ECORRUPT;
@@ -157,13 +171,16 @@ int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_table
     const uint32_t reserved = get32(img + 44);
     v->N = get64(img + 48);
     v->tables_crc = get32(img + 56);
-    if (version != 1 || (v->flags & ~1u) || reserved != 0 || !valid_chunk(v->C)) return CKPT_ECORRUPT;
+    if (version != 1 || (v->flags & ~(kFlagDelta | kFlagCodec)) || reserved != 0 || !valid_chunk(v->C))
+        return CKPT_ECORRUPT;
     if (v->n_chunks > (1ull << 40) || v->n_allocs > (1u << 24)) return CKPT_ECORRUPT;
-    v->tl = tables_len(v->n_allocs, v->n_chunks);
+    const bool codec = v->flags & kFlagCodec;
+    v->tl = tables_len(v->n_allocs, v->n_chunks, codec);
     if (len != kHeader + v->tl + v->D) return CKPT_ECORRUPT;
     v->recs = img + kHeader;
     v->crcs = v->recs + 32ull * v->n_allocs;
-    v->kinds = v->crcs + 4 * v->n_chunks;
+    v->rlens = codec ? v->crcs + 4 * v->n_chunks : nullptr;
+    v->kinds = v->crcs + (codec ? 8 : 4) * v->n_chunks;
     v->payload = img + kHeader + v->tl;
     // allocation records: chunk grid, sizes, padding
     uint64_t g = 0, total = 0;
@@ -182,13 +199,12 @@ int parse_image(const uint8_t* img, uint64_t len, ImageView* v, bool check_table
         if (host_crc32c(v->recs, v->tl) != v->tables_crc) return CKPT_ECORRUPT;
         // kinds and payload length
         uint64_t dsum = 0;
-        const bool delta = v->flags & 1u;
         for (uint64_t a = 0, gg = 0; a < v->n_allocs; ++a) {
             const uint64_t size = get64(v->recs + 32 * a + 8), nk = ceil_div(size, v->C);
             for (uint64_t k = 0; k < nk; ++k, ++gg) {
-                const uint8_t kd = v->kinds[gg];
-                if (kd > kUnchanged || (kd == kUnchanged && !delta)) return CKPT_ECORRUPT;
-                if (kd == kData) dsum += round16(k + 1 == nk ? size - k * v->C : v->C);
+                const uint64_t rl = record_len(*v, gg, k + 1 == nk ? size - k * v->C : v->C);
+                if (rl == kBadRecord) return CKPT_ECORRUPT;
+                dsum += rl;
             }
         }
         if (dsum != v->D) return CKPT_ECORRUPT;
@@ -259,6 +275,26 @@ hipError_t get_consts(ckpt_ctx* c, int T, uint32_t C, const EngineConsts** out) 
     }
     *out = it->second.as<EngineConsts>();
     return hipSuccess;
+}
+
+hipError_t get_codec_consts(ckpt_ctx* c, uint32_t C, const CodecConsts** out) {
+    auto it = c->cconsts.find(C);
+    if (it == c->cconsts.end()) {
+        CodecConsts h;
+        build_codec_consts(&h, C);
+        DevBuf b;
+        hipError_t e = b.ensure(sizeof(CodecConsts));
+        if (e == hipSuccess) e = hipMemcpy(b.p, &h, sizeof(CodecConsts), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { b.release(); return e; }
+        it = c->cconsts.emplace(C, b).first;
+    }
+    *out = it->second.as<CodecConsts>();
+    return hipSuccess;
+}
+
+// Grid of the codec decode: two work-groups per CU (LDS-bound), grid-stride.
+int unpack_grid(const ckpt_ctx* c, uint64_t chunks) {
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 2ull * c->num_cu));
 }
 
 hipError_t grid_for(ckpt_ctx* c, int T, int K, int mode, uint64_t work, int* grid) {
@@ -449,9 +485,10 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (hipEvent_t e : c->tevents) hipEventDestroy(e);
     DevBuf* bufs[] = {&c->descs, &c->status, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
-                      &c->staging, &c->dig, &c->amap};
+                      &c->staging, &c->dig, &c->amap, &c->rlen};
     for (DevBuf* b : bufs) b->release();
     for (auto& kv : c->consts) kv.second.release();
+    for (auto& kv : c->cconsts) kv.second.release();
     for (auto& kv : c->digests) kv.second.crc.release();
     for (auto& ge : c->graphs) {
         if (ge.exec) hipGraphExecDestroy(ge.exec);
@@ -566,8 +603,11 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     const uint64_t t_start = now_ns();
     const uint32_t C = (o && o->chunk_size) ? o->chunk_size : kDefaultChunk;
     if (!valid_chunk(C)) return CKPT_EINVAL;
-    if (o && (o->reserved || (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING))))
+    if (o && (o->reserved ||
+              (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING | CKPT_OPT_CODEC))))
         return CKPT_EINVAL;
+    const bool codec = o && (o->flags & CKPT_OPT_CODEC);
+    if (codec && (!codec_chunk_supported(C) || (o->flags & (CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH)))) return CKPT_EINVAL;
     const uint32_t n = table->n;
     if (n && !table->v) return CKPT_EINVAL;
     {
@@ -609,7 +649,8 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         if (nk) upper += (nk - 1) * C + round16(d[a].tail_len);
     }
     const uint64_t nc = g;
-    const uint64_t tl = tables_len(n, nc);
+    const uint64_t tl = tables_len(n, nc, codec);
+    const uint64_t rl_bytes = codec ? 4 * nc : 0;   // the record-length table of the codec layout
     const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
     int T, K;
     pick_tile(C, o ? o->wg_threads : 0, &T, &K);
@@ -619,6 +660,9 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
     const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
     if ((uint64_t)nslots * slot > c->budget && nslots > 1) return CKPT_ENOMEM;
+    // the codec's payload offsets follow from the record lengths of the whole
+    // table: its image has to fit one staging window
+    if (codec && wins.size() > 1) return CKPT_ENOMEM;
 
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(ensure_copy_streams(c, ncs));
@@ -639,7 +683,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
     HIPCHK(ensure_events(c, W + (size_t)nslots + 2));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * W));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? 2 : 0)));
     const EngineConsts* ec;
     HIPCHK(get_consts(c, T, C, &ec));
 
@@ -748,7 +792,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
 
     uint64_t pos = 0, t_link0 = 0;
     hipError_t e = hipSuccess;
-    const uint64_t len_a = 32ull * n + 4 * nc, len_b = tl - len_a;
+    const uint64_t len_a = 32ull * n + 4 * nc, len_b = tl - len_a - rl_bytes;
     uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall + 8 * (W + 1));
     const bool use_graph = o && (o->flags & CKPT_OPT_GRAPH) && W == 1 && !per_alloc;
     // A delta dump in one window takes three passes: digests and kinds of
@@ -813,6 +857,78 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(hw, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
             return e;
+        return hipEventRecord(ev[0], c->s_main);
+    };
+    // Codec dump in one window: digests and kinds (classify), record lengths
+    // (size pass; DATA becomes PACKED where the record is shorter), payload
+    // offsets from a host prefix over the lengths, then the DATA chunks
+    // gathered and the PACKED records encoded to their offsets.
+    std::vector<uint32_t> rlen_host;
+    auto launch_codec = [&]() -> hipError_t {
+        hipError_t e;
+        bool wrapped;
+        const uint32_t ep = next_epoch(c, &wrapped);
+        if (wrapped && (e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main)) != hipSuccess)
+            return e;
+        if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
+        if ((e = c->rlen.ensure(4 * nc)) != hipSuccess) return e;
+        ChunkJob j;
+        memset(&j, 0, sizeof(j));
+        j.allocs = c->descs.as<AllocDesc>();
+        j.n_allocs = n;
+        j.C = C;
+        j.amap = c->amap.as<uint32_t>();
+        j.g0 = 0;
+        j.g1 = nc;
+        j.ec = ec;
+        j.crc_out = crc_dev;
+        j.kind_out = kind_dev;
+        j.kind_in = kind_dev;
+        j.prev_crc = prev_dev;
+        j.slot = c->staging.as<uint8_t>();
+        j.off = c->off.as<uint64_t>();
+        j.slot_base = 0;
+        j.err = err;
+        j.epoch = ep;
+        PackJob pj;
+        memset(&pj, 0, sizeof(pj));
+        pj.allocs = c->descs.as<AllocDesc>();
+        pj.amap = c->amap.as<uint32_t>();
+        pj.n_chunks = nc;
+        pj.C = C;
+        pj.kind = kind_dev;
+        pj.rlen = c->rlen.as<uint32_t>();
+        pj.off = c->off.as<uint64_t>();
+        pj.slot = c->staging.as<uint8_t>();
+        pj.err = err;
+        const int pgrid = (int)std::min<uint64_t>(nc, 8ull * c->num_cu);
+        int grid;
+        if ((e = grid_for(c, T, K, kModeClassify, nc, &grid)) != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[0], c->s_main)) != hipSuccess) return e;
+        if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 0), grid, c->s_main)) != hipSuccess) return e;
+        if ((e = launch_pack(pj, false, pgrid, c->s_main)) != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
+        rlen_host.resize(nc);
+        if ((e = hipMemcpyAsync(rlen_host.data(), c->rlen.p, 4 * nc, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return e;
+        std::vector<uint64_t> offh(nc);
+        uint64_t D = 0;
+        for (uint64_t i = 0; i < nc; ++i) {
+            offh[i] = D;
+            D += rlen_host[i];
+        }
+        if (D > slot) return hipErrorIllegalState;   // records never exceed their chunks
+        if ((e = hipMemcpyAsync(c->off.p, offh.data(), 8 * nc, hipMemcpyHostToDevice, c->s_main)) != hipSuccess)
+            return e;
+        if (timing && (e = hipEventRecord(c->tevents[2], c->s_main)) != hipSuccess) return e;
+        if ((e = grid_for(c, T, K, kModeGather, nc, &grid)) != hipSuccess) return e;
+        if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2), grid, c->s_main)) != hipSuccess) return e;
+        if ((e = launch_pack(pj, true, pgrid, c->s_main)) != hipSuccess) return e;
+        if (timing && (e = hipEventRecord(c->tevents[3], c->s_main)) != hipSuccess) return e;
+        // offh is pageable: the upload has completed once the stream has
+        if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return e;
+        reinterpret_cast<uint64_t*>(c->hsmall)[0] = D;
         return hipEventRecord(ev[0], c->s_main);
     };
     if (use_graph) {
@@ -927,7 +1043,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         // a slot of its own (nslots >= 2): its slot-free event then belongs to
         // a copy that has already been issued.
         const bool ahead = nslots >= 2;
-        if (W) e = two_pass ? launch_two_pass() : launch_window(0, 0);
+        if (W) e = codec ? launch_codec() : two_pass ? launch_two_pass() : launch_window(0, 0);
         for (uint64_t w = 0; w < W && e == hipSuccess; ++w) {
             if (w > 0 && !ahead) {
                 e = launch_window(w, pos);
@@ -1000,7 +1116,9 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     // tables into the image
     if ((e = hipMemcpyAsync(himg + kHeader, c->arc.p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
         return fail(e);
-    if ((e = hipMemcpyAsync(himg + kHeader + len_a, kind_dev, len_b, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+    if (codec) memcpy(himg + kHeader + len_a, rlen_host.data(), rl_bytes);   // little-endian host
+    if ((e = hipMemcpyAsync(himg + kHeader + len_a + rl_bytes, kind_dev, len_b, hipMemcpyDeviceToHost, c->s_main)) !=
+        hipSuccess)
         return fail(e);
     if ((e = hipMemcpyAsync(hdig + 2, err, 4, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess) return fail(e);
     if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
@@ -1011,11 +1129,13 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
 
     // header
     const uint32_t sd = hdig[0];
-    const uint32_t tcrc = crc_combine(sd, hdig[1], len_b);
+    uint32_t tcrc = sd;
+    if (codec) tcrc = crc_combine(tcrc, host_crc32c(rlen_host.data(), rl_bytes), rl_bytes);
+    tcrc = crc_combine(tcrc, hdig[1], len_b);
     uint8_t* h = himg;
     memcpy(h, "MICKPT01", 8);
     put32(h + 8, 1);
-    put32(h + 12, prev ? 1u : 0u);
+    put32(h + 12, (prev ? kFlagDelta : 0u) | (codec ? kFlagCodec : 0u));
     put32(h + 16, C);
     put32(h + 20, n);
     put64(h + 24, nc);
@@ -1037,12 +1157,13 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         res->n_chunks = nc;
         res->link_bytes = D + tl + kHeader;
         res->ns_link = t_link0 ? t_link1 - t_link0 : 0;
-        res->ns_kernel = timing ? timed_ns(c, W) : 0;
+        res->ns_kernel = timing ? timed_ns(c, codec && W ? 2 : W) : 0;
         res->ns_total = now_ns() - t_start;
-        const uint8_t* kinds = himg + kHeader + 32ull * n + 4 * nc;
+        const uint8_t* kinds = himg + kHeader + len_a + rl_bytes;
         for (uint64_t i = 0; i < nc; ++i) {
             if (kinds[i] == kZero) ++res->n_zero;
             else if (kinds[i] == kData) ++res->n_data;
+            else if (kinds[i] == kPacked) ++res->n_packed;
             else ++res->n_unchanged;
         }
     }
@@ -1068,7 +1189,9 @@ extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_
 static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
                         void* stream, ckpt_result* res, bool some) {
     const uint64_t t_start = now_ns();
-    if (o && (o->reserved || (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING))))
+    // CKPT_OPT_CODEC is accepted and has no effect: the image says how it is stored
+    if (o && (o->reserved ||
+              (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING | CKPT_OPT_CODEC))))
         return CKPT_EINVAL;
     const uint32_t n = table->n;
     if (n && !table->v) return CKPT_EINVAL;
@@ -1077,7 +1200,9 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     if (rc) return rc;
     const uint32_t C = v.C;
     const uint64_t nc = v.n_chunks, tl = v.tl;
-    const uint64_t len_a = 32ull * v.n_allocs + 4 * nc, len_b = tl - len_a;
+    const bool codec = v.flags & kFlagCodec;
+    const uint64_t rl_bytes = codec ? 4 * nc : 0;
+    const uint64_t len_a = 32ull * v.n_allocs + 4 * nc, len_b = tl - len_a - rl_bytes;
     for (uint32_t a = 0; a < n && (some || a < v.n_allocs); ++a) {
         const ckpt_alloc& e = table->v[a];
         if (e.size && (!e.dev_ptr || (reinterpret_cast<uintptr_t>(e.dev_ptr) & 15))) return CKPT_EINVAL;
@@ -1130,6 +1255,7 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     HIPCHK(c->arc.ensure(tl + 16));
     HIPCHK(c->kinds.ensure(tl + 16));
     HIPCHK(c->off.ensure(8 * std::max<uint64_t>(nc, 1)));
+    if (codec) HIPCHK(c->rlen.ensure(4 * std::max<uint64_t>(nc, 1)));
     HIPCHK(c->wb.ensure(8 * (W + 2)));
     HIPCHK(c->staging.ensure((uint64_t)nslots * slot));
     HIPCHK(c->status.ensure(8 * (ceil_div(nc, 256) + 64)));
@@ -1167,7 +1293,32 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     uint64_t* hwb = reinterpret_cast<uint64_t*>(c->hsmall + 128);
     rc = device_table_digests(c, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, hdig, res);
     if (rc) return rc;
-    if (nc) {
+    // codec layout: kinds and record lengths checked and payload offsets
+    // summed on the host; the offsets and lengths go up to the device
+    std::vector<uint64_t> pre;
+    uint64_t n_packed = 0, hz = 0, hd = 0, hu = 0;
+    if (codec) {
+        pre.assign(nc + 1, 0);
+        for (uint64_t a = 0; a < v.n_allocs; ++a) {
+            const uint64_t nk = ceil_div(d[a].size, C);
+            for (uint64_t k = 0; k < nk; ++k) {
+                const uint64_t gg = d[a].first + k;
+                const uint64_t r = record_len(v, gg, k + 1 == nk ? d[a].tail_len : C);
+                if (r == kBadRecord) return CKPT_ECORRUPT;
+                const uint8_t kd = v.kinds[gg];
+                hz += kd == kZero;
+                hd += kd == kData || kd == kPacked;
+                hu += kd == kUnchanged;
+                n_packed += kd == kPacked;
+                pre[gg + 1] = pre[gg] + r;
+            }
+        }
+        if (nc) {
+            HIPCHK(hipMemcpyAsync(c->off.p, pre.data(), 8 * nc, hipMemcpyHostToDevice, c->s_main));
+            HIPCHK(hipMemcpyAsync(c->rlen.p, v.rlens, 4 * nc, hipMemcpyHostToDevice, c->s_main));
+        }
+    }
+    if (nc && !codec) {
         bool wrapped;
         const uint32_t ep = next_epoch(c, &wrapped);
         if (wrapped) HIPCHK(launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main));
@@ -1196,13 +1347,26 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     HIPCHK(hipMemcpyAsync(hq, counts, 32, hipMemcpyDeviceToHost, c->s_main));
     HIPCHK(hipStreamSynchronize(c->s_main));
     // validation in the oracle's order: tables digest and structure, then the match
-    if (crc_combine(hdig[0], hdig[1], len_b) != v.tables_crc) return CKPT_ECORRUPT;
-    const uint64_t nz = hq[0], nd = hq[1], nu = hq[2], ninv = hq[3];
-    if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != nc) return CKPT_ECORRUPT;
+    uint32_t tcrc = hdig[0];
+    if (codec) tcrc = crc_combine(tcrc, host_crc32c(v.rlens, rl_bytes), rl_bytes);
+    if (crc_combine(tcrc, hdig[1], len_b) != v.tables_crc) return CKPT_ECORRUPT;
+    const uint64_t nz = codec ? hz : hq[0], nd = codec ? hd : hq[1], nu = codec ? hu : hq[2],
+                   ninv = codec ? 0 : hq[3];
+    if (ninv || (nu && !(v.flags & kFlagDelta)) || nz + nd + nu != nc) return CKPT_ECORRUPT;
+    // PACKED records are decoded by kernels built for a range of chunk sizes
+    if (n_packed && !codec_chunk_supported(C)) return CKPT_EINVAL;
+    const CodecConsts* cc = nullptr;
+    if (n_packed) HIPCHK(get_codec_consts(c, C, &cc));
     // window payload ranges [wbeg, wend); the payload total must equal D
     std::vector<uint64_t> wbeg(W), wend(W);
     if (nc) {
-        if (per_alloc) {
+        if (codec) {
+            if (pre[nc] != v.D) return CKPT_ECORRUPT;
+            for (uint64_t w = 0; w < W; ++w) {
+                wbeg[w] = pre[wins[w].g0];
+                wend[w] = pre[wins[w].g1];
+            }
+        } else if (per_alloc) {
             // per-allocation (or selected-allocation) windows: from a host
             // prefix over the payload lengths
             std::vector<uint64_t> pre(nc + 1, 0);
@@ -1352,6 +1516,8 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
             HIPCHK(grid_for(c, T, K, kModeRestore, tot, &grid));
             if (timing) HIPCHK(hipEventRecord(c->tevents[2 * l], c->s_main));
             HIPCHK(launch_chunks(T, K, kModeRestore, jl, grid, c->s_main));
+            if (n_packed)
+                HIPCHK(launch_unpack(jl, c->rlen.as<uint32_t>(), cc, unpack_grid(c, tot), c->s_main));
             if (timing) HIPCHK(hipEventRecord(c->tevents[2 * l + 1], c->s_main));
         }
     }
@@ -1385,7 +1551,10 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         int grid;
         HIPCHK(grid_for(c, T, K, kModeRestore, j.g1 - j.g0, &grid));
         if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w], c->s_main));
-        HIPCHK(launch_chunks(T, K, kModeRestore, one_job(j, wtk + w), grid, c->s_main));
+        const JobList jl = one_job(j, wtk + w);
+        HIPCHK(launch_chunks(T, K, kModeRestore, jl, grid, c->s_main));
+        if (n_packed)
+            HIPCHK(launch_unpack(jl, c->rlen.as<uint32_t>(), cc, unpack_grid(c, j.g1 - j.g0), c->s_main));
         if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w + 1], c->s_main));
         HIPCHK(hipEventRecord(ev[W + s], c->s_main));
     }
@@ -1419,8 +1588,9 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         res->n_payload = moved;
         res->n_chunks = nc;
         res->n_zero = nz;
-        res->n_data = nd;
+        res->n_data = nd - n_packed;
         res->n_unchanged = nu;
+        res->n_packed = n_packed;
         res->link_bytes = moved + tl + kHeader;
         res->ns_link = t_link1 - t_link0;
         res->ns_kernel = timing ? timed_ns(c, merged ? ceil_div(W, (uint64_t)kMaxJobs) : W) : 0;
@@ -1572,11 +1742,14 @@ extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_
     if (rc) return rc;
     rc = parse_image(delta->p, delta->n, &d, true);
     if (rc) return rc;
-    if ((b.flags & 1u) || !(d.flags & 1u) || b.C != d.C) return CKPT_EINVAL;
+    if ((b.flags & kFlagDelta) || !(d.flags & kFlagDelta) || b.C != d.C) return CKPT_EINVAL;
     if (d.base_state != b.state_digest) return CKPT_EBASE;
     const uint32_t C = d.C;
-    // payload offset of each DATA chunk of the base, and base allocations by id
-    std::vector<uint64_t> bpos(b.n_chunks);
+    // the merged image has the codec layout when either input has it
+    const bool codec = (b.flags | d.flags) & kFlagCodec;
+    // payload offset and record length of every chunk of the base, and base
+    // allocations by id
+    std::vector<uint64_t> bpos(b.n_chunks), brl(b.n_chunks);
     std::unordered_map<uint64_t, uint64_t> bidx;
     bidx.reserve(b.n_allocs * 2 + 1);
     uint64_t pos = 0;
@@ -1586,11 +1759,13 @@ extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_
         const uint64_t nk = ceil_div(size, C);
         for (uint64_t k = 0; k < nk; ++k) {
             bpos[first + k] = pos;
-            if (b.kinds[first + k] == kData) pos += round16(k + 1 == nk ? size - k * C : C);
+            brl[first + k] = record_len(b, first + k, k + 1 == nk ? size - k * C : C);
+            pos += brl[first + k];
         }
     }
-    // merged kinds and payload size
+    // merged kinds, record lengths and payload size
     std::vector<uint8_t> kinds(d.n_chunks);
+    std::vector<uint32_t> rl(d.n_chunks);
     std::vector<const uint8_t*> src(d.n_chunks, nullptr);
     uint64_t D = 0, dpos = 0;
     for (uint64_t a = 0; a < d.n_allocs; ++a) {
@@ -1599,42 +1774,41 @@ extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_
         const uint64_t nk = ceil_div(size, C);
         auto bi = bidx.find(id);
         for (uint64_t k = 0; k < nk; ++k) {
-            const uint64_t gi = first + k, l16 = round16(k + 1 == nk ? size - k * C : C);
+            const uint64_t gi = first + k;
             uint8_t kd = d.kinds[gi];
-            if (kd == kData) {
-                src[gi] = d.payload + dpos;
-                dpos += l16;
-            } else if (kd == kUnchanged) {
+            uint64_t r = record_len(d, gi, k + 1 == nk ? size - k * C : C);
+            src[gi] = d.payload + dpos;
+            dpos += r;
+            if (kd == kUnchanged) {
                 if (bi == bidx.end() || get64(b.recs + 32 * bi->second + 8) != size) return CKPT_EBASE;
                 const uint64_t gb = get64(b.recs + 32 * bi->second + 16) + k;
                 kd = b.kinds[gb];
-                if (kd == kData) src[gi] = b.payload + bpos[gb];
+                r = brl[gb];
+                src[gi] = b.payload + bpos[gb];
             }
             kinds[gi] = kd;
-            if (kd == kData) D += l16;
+            rl[gi] = (uint32_t)r;
+            D += r;
         }
     }
-    ckpt_image* im = image_new(kHeader + d.tl + D);
+    const uint64_t tl = tables_len(d.n_allocs, d.n_chunks, codec);
+    ckpt_image* im = image_new(kHeader + tl + D);
     if (!im) return CKPT_ENOMEM;
     uint8_t* o = im->p;
-    memset(o, 0, kHeader + d.tl);
+    memset(o, 0, kHeader + tl);
     const uint64_t len_a = 32ull * d.n_allocs + 4 * d.n_chunks;
     memcpy(o + kHeader, d.recs, len_a);
-    memcpy(o + kHeader + len_a, kinds.data(), d.n_chunks);
-    uint64_t op = kHeader + d.tl;
-    for (uint64_t a = 0; a < d.n_allocs; ++a) {
-        const uint64_t size = get64(d.recs + 32 * a + 8), first = get64(d.recs + 32 * a + 16);
-        const uint64_t nk = ceil_div(size, C);
-        for (uint64_t k = 0; k < nk; ++k) {
-            if (!src[first + k]) continue;
-            const uint64_t l16 = round16(k + 1 == nk ? size - k * C : C);
-            memcpy(o + op, src[first + k], l16);
-            op += l16;
-        }
+    if (codec) memcpy(o + kHeader + len_a, rl.data(), 4 * d.n_chunks);   // little-endian host
+    memcpy(o + kHeader + len_a + (codec ? 4 * d.n_chunks : 0), kinds.data(), d.n_chunks);
+    uint64_t op = kHeader + tl;
+    for (uint64_t g = 0; g < d.n_chunks; ++g) {
+        if (!rl[g]) continue;
+        memcpy(o + op, src[g], rl[g]);
+        op += rl[g];
     }
     memcpy(o, "MICKPT01", 8);
     put32(o + 8, 1);
-    put32(o + 12, 0);
+    put32(o + 12, codec ? kFlagCodec : 0u);
     put32(o + 16, C);
     put32(o + 20, d.n_allocs);
     put64(o + 24, d.n_chunks);
@@ -1642,7 +1816,7 @@ extern "C" int ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_
     put32(o + 40, 0);
     put32(o + 44, 0);
     put64(o + 48, d.N);
-    put32(o + 56, host_crc32c(o + kHeader, d.tl));
+    put32(o + 56, host_crc32c(o + kHeader, tl));
     put32(o + 60, host_crc32c(o, 60));
     im->n = op;
     *out = im;

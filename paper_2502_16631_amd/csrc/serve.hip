@@ -239,6 +239,8 @@ void admit_restore(ckpt_server* s, Req* r) {
     Lane& L = s->lanes[r->lane];
     int rc = parse_image(r->rq.img->p, r->rq.img->n, &r->v, false);
     if (rc) { finish(s, r, rc); return; }
+    // the served loop restores the plain layout; codec images go through ckpt_restore
+    if (r->v.flags & kFlagCodec) { finish(s, r, CKPT_EINVAL); return; }
     const ImageView& v = r->v;
     r->C = v.C;
     r->n = (uint32_t)r->table.size();

@@ -29,10 +29,11 @@ CKPT_EMISMATCH = -5
 CKPT_EBASE = -6
 CKPT_ETIMEOUT = -7
 CKPT_EIO = -8
-KIND_ZERO, KIND_DATA, KIND_UNCHANGED = 0, 1, 2
+KIND_ZERO, KIND_DATA, KIND_UNCHANGED, KIND_PACKED = 0, 1, 2, 3
 OPT_PER_ALLOC = 1
 OPT_GRAPH = 2
 OPT_NO_TIMING = 4
+OPT_CODEC = 8
 NO_CHUNK = (1 << 64) - 1
 
 _u64 = ctypes.c_uint64
@@ -57,7 +58,7 @@ class ckpt_result(ctypes.Structure):
                 ("n_logical", _u64), ("n_payload", _u64), ("n_chunks", _u64),
                 ("n_zero", _u64), ("n_data", _u64), ("n_unchanged", _u64),
                 ("link_bytes", _u64), ("ns_total", _u64), ("ns_kernel", _u64), ("ns_link", _u64),
-                ("reserved", _u64 * 4)]
+                ("n_packed", _u64), ("reserved", _u64 * 3)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
