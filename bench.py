@@ -164,12 +164,13 @@ def main():
     ap.add_argument("--cpu-sample", type=float, default=16e9, help="bytes of the oracle sample (0 = skip); ~10-15 s of CPU work")
     ap.add_argument("--check", action="store_true", help="verify restored bytes after each step")
     ap.add_argument("--form", default="plain",
-                    choices=["plain", "incremental", "batched", "serve", "ondemand", "storage"],
+                    choices=["plain", "incremental", "batched", "serve", "ondemand", "storage", "codec"],
                     help="plain: full dump + restore (default); incremental: 40 GB HPC image, delta dump and "
                          "base + delta restore; batched: 10,000 allocations, graph-captured single launch vs "
                          "per-allocation launches, autotuned; serve: multi-tenant Poisson trace, p50/p99; "
                          "ondemand: parameters restored first vs one full restore; "
-                         "storage: dump + image to file, file + restore")
+                         "storage: dump + image to file, file + restore; codec: plain vs byte-plane codec "
+                         "dump + restore of the training state")
     ap.add_argument("--path", default="/tmp/mickpt_bench.img", help="storage: image file (removed afterwards)")
     ap.add_argument("--io-threads", type=int, default=8, help="storage: file I/O threads")
     ap.add_argument("--scale", type=float, default=1.0, help="scale the total bytes of the non-plain forms")
@@ -188,7 +189,7 @@ def main():
         import bench_forms
         line = {"incremental": bench_forms.incremental, "batched": bench_forms.batched,
                 "serve": bench_forms.serve, "ondemand": bench_forms.ondemand,
-                "storage": bench_forms.storage}[args.form](
+                "storage": bench_forms.storage, "codec": bench_forms.codec}[args.form](
                     args, torch, mk, link_baseline(torch))
         print(json.dumps(line), flush=True)
         return

@@ -383,3 +383,61 @@ def storage(args, torch, mk, link):
         "file_write_GBps": round(size / md(ts) / 1e9, 3), "file_read_GBps": round(size / md(tl) / 1e9, 3),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
     }
+
+
+def codec(args, torch, mk, link):
+    """Byte-plane codec on the training state (~27 GB: bf16 parameters and
+    activations, fp32 master weights and moments): plain and codec dumps and
+    restores of the same state, timed end to end (device stage + host link),
+    with the payload each moves over the link."""
+    table = workloads.training_state("cuda", seed=2)
+    torch.cuda.synchronize()
+    N = _nbytes(table)
+    ctx = mk.ckpt_ctx_create(0, max(args.budget, N + (1 << 30)))
+    plain = mk.make_opts(chunk_size=C)
+    packed = mk.make_opts(chunk_size=C, flags=mk.OPT_CODEC)
+    t = {k: [] for k in ("dump_plain", "dump_codec", "restore_plain", "restore_codec",
+                         "kernel_dump_codec", "kernel_restore_codec", "kernel_dump_plain", "kernel_restore_plain")}
+    D = {}
+    n_packed = 0
+    for k in range(args.warmup + args.steps):
+        row = {}
+        for name, opts in (("plain", plain), ("codec", packed)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+            t1 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            D[name] = res.n_payload
+            if name == "codec":
+                n_packed = res.n_packed
+            row["dump_" + name] = t1 - t0
+            row["kernel_dump_" + name] = res.ns_kernel * 1e-9
+            rc, rres = mk.ckpt_restore(ctx, img, table, opts=opts)
+            t2 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            row["restore_" + name] = t2 - t1
+            row["kernel_restore_" + name] = rres.ns_kernel * 1e-9
+            img.free()
+        if k >= args.warmup:
+            for key, v in row.items():
+                t[key].append(v)
+        _log("step %d: " % k + ", ".join("%s %.3f s" % (key, v) for key, v in row.items()))
+    mk.ckpt_ctx_destroy(ctx)
+    md = {key: _pct(v, 50) for key, v in t.items()}
+    return {
+        "metric": "dump and restore GB/s with the byte-plane codec at 1 GPU", "form": "codec",
+        "value": round(2 * N / (md["dump_codec"] + md["restore_codec"]) / 1e9, 3),
+        "unit": "GB/s (logical, dump + restore)",
+        "config": {"workload": "decoder-1.3B training state (303 allocations)", "chunk": C, "N_bytes": N},
+        "payload_plain_bytes": D["plain"], "payload_codec_bytes": D["codec"],
+        "link_bytes_ratio": round(D["codec"] / D["plain"], 4), "packed_chunks": n_packed,
+        "dump_ms_p50": {"plain": round(md["dump_plain"] * 1e3, 1), "codec": round(md["dump_codec"] * 1e3, 1)},
+        "restore_ms_p50": {"plain": round(md["restore_plain"] * 1e3, 1), "codec": round(md["restore_codec"] * 1e3, 1)},
+        "device_stage_ms_p50": {"dump_plain": round(md["kernel_dump_plain"] * 1e3, 2),
+                                "dump_codec": round(md["kernel_dump_codec"] * 1e3, 2),
+                                "restore_plain": round(md["kernel_restore_plain"] * 1e3, 2),
+                                "restore_codec": round(md["kernel_restore_codec"] * 1e3, 2)},
+        "plain_GBps": round(2 * N / (md["dump_plain"] + md["restore_plain"]) / 1e9, 3),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
+    }

@@ -30,6 +30,7 @@ namespace mk {
 constexpr uint32_t kCodecMinChunk = 4096;    // one 16-byte row per lane
 constexpr uint32_t kCodecMaxChunk = 65536;   // records are staged in LDS
 constexpr int kCodecThreads = 256;
+constexpr uint64_t kCodecPieces = 8;         // a codec dump's encode / copy-out pipeline depth
 constexpr uint32_t kRecordHead = 48;
 enum : uint32_t { kPlaneRaw = 0, kPlaneConst = 1, kPlaneDict = 2 };
 
@@ -45,11 +46,11 @@ struct CodecConsts {
 };
 void build_codec_consts(CodecConsts* cc, uint32_t C);
 
-// Size and encode passes over the chunks [0, n_chunks) of one table.
+// Size and encode passes over the chunks [g0, g1) of one table.
 struct PackJob {
     const AllocDesc* allocs;
     const uint32_t* amap;    // allocation of chunk g (required)
-    uint64_t n_chunks;
+    uint64_t g0, g1;
     uint32_t C;
     uint32_t pad;
     uint8_t* kind;           // size: DATA becomes PACKED where the record is shorter

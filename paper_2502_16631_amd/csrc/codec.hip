@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
     __shared__ uint4 s_rec[ENCODE ? kCodecMaxChunk / 16 : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t C = j.C, L = C / 8;
-    for (uint64_t g = blockIdx.x; g < j.n_chunks; g += gridDim.x) {
+    for (uint64_t g = j.g0 + blockIdx.x; g < j.g1; g += gridDim.x) {
         __syncthreads();   // the previous chunk's LDS is no longer read
         const uint8_t kd = j.kind[g];
         const AllocDesc ad = j.allocs[j.amap[g]];
@@ -403,7 +403,7 @@ void build_codec_consts(CodecConsts* cc, uint32_t C) {
 
 hipError_t launch_pack(const PackJob& j, bool encode, int grid, hipStream_t s) {
     if (!codec_chunk_supported(j.C) || !j.amap || grid < 1) return hipErrorInvalidValue;
-    if (j.n_chunks == 0) return hipSuccess;
+    if (j.g1 <= j.g0) return hipSuccess;
     switch (j.C / kCodecMinChunk) {
         case 1: return pack_k<1>(j, encode, grid, s);
         case 2: return pack_k<2>(j, encode, grid, s);

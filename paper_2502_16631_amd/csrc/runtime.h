@@ -153,6 +153,7 @@ void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K);
 hipError_t get_consts(ckpt_ctx* c, int T, uint32_t C, const EngineConsts** out);
 hipError_t get_codec_consts(ckpt_ctx* c, uint32_t C, const CodecConsts** out);
 int unpack_grid(const ckpt_ctx* c, uint64_t chunks);
+int pack_grid(const ckpt_ctx* c, uint64_t chunks);
 hipError_t grid_for(ckpt_ctx* c, int T, int K, int mode, uint64_t work, int* grid);
 void make_desc(AllocDesc* d, uint64_t id, const void* ptr, uint64_t size, uint64_t first, uint64_t prev_first,
                uint32_t C);

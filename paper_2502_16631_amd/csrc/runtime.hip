@@ -297,6 +297,11 @@ int unpack_grid(const ckpt_ctx* c, uint64_t chunks) {
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 2ull * c->num_cu));
 }
 
+// Grid of the codec size and encode passes (grid-stride over chunks).
+int pack_grid(const ckpt_ctx* c, uint64_t chunks) {
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 8ull * c->num_cu));
+}
+
 hipError_t grid_for(ckpt_ctx* c, int T, int K, int mode, uint64_t work, int* grid) {
     auto key = std::make_tuple(T, K, mode);
     auto it = c->occ.find(key);
@@ -676,14 +681,15 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     for (const Window& w : wins) max_win = std::max(max_win, w.g1 - w.g0);
     HIPCHK(c->status.ensure(8 * (max_win + 64)));
     const uint64_t W = wins.size();
-    // ctl: tickets[max(W, 3) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
-    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (std::max<uint64_t>(W, 3) + 1)),
+    // ctl: tickets[max(W, 3, codec pieces + 2) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
+    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? kCodecPieces + 2 : 0);
+    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (n_tk + 1)),
                    ctl_err = ctl_wt + 8 * (W + 1), ctl_cnt = ctl_err + 16;
     HIPCHK(c->ctl.ensure(ctl_err + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
-    HIPCHK(ensure_events(c, W + (size_t)nslots + 2));
+    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, codec ? kCodecPieces + 1 : 0)));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? 2 : 0)));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? kCodecPieces + 1 : 0)));
     const EngineConsts* ec;
     HIPCHK(get_consts(c, T, C, &ec));
 
@@ -861,10 +867,13 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
     };
     // Codec dump in one window: digests and kinds (classify), record lengths
     // (size pass; DATA becomes PACKED where the record is shorter), payload
-    // offsets from a host prefix over the lengths, then the DATA chunks
-    // gathered and the PACKED records encoded to their offsets.
+    // offsets from a host prefix over the lengths; then in kCodecPieces
+    // pieces of about equal payload the DATA chunks are gathered and the
+    // PACKED records encoded, and each piece is copied out as soon as it is
+    // done, while the next one is encoded.
     std::vector<uint32_t> rlen_host;
-    auto launch_codec = [&]() -> hipError_t {
+    uint64_t codec_pieces = 0;
+    auto launch_codec = [&](uint64_t* D_out) -> hipError_t {
         hipError_t e;
         bool wrapped;
         const uint32_t ep = next_epoch(c, &wrapped);
@@ -894,19 +903,19 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         memset(&pj, 0, sizeof(pj));
         pj.allocs = c->descs.as<AllocDesc>();
         pj.amap = c->amap.as<uint32_t>();
-        pj.n_chunks = nc;
+        pj.g0 = 0;
+        pj.g1 = nc;
         pj.C = C;
         pj.kind = kind_dev;
         pj.rlen = c->rlen.as<uint32_t>();
         pj.off = c->off.as<uint64_t>();
         pj.slot = c->staging.as<uint8_t>();
         pj.err = err;
-        const int pgrid = (int)std::min<uint64_t>(nc, 8ull * c->num_cu);
         int grid;
         if ((e = grid_for(c, T, K, kModeClassify, nc, &grid)) != hipSuccess) return e;
         if (timing && (e = hipEventRecord(c->tevents[0], c->s_main)) != hipSuccess) return e;
         if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 0), grid, c->s_main)) != hipSuccess) return e;
-        if ((e = launch_pack(pj, false, pgrid, c->s_main)) != hipSuccess) return e;
+        if ((e = launch_pack(pj, false, pack_grid(c, nc), c->s_main)) != hipSuccess) return e;
         if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
         rlen_host.resize(nc);
         if ((e = hipMemcpyAsync(rlen_host.data(), c->rlen.p, 4 * nc, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
@@ -921,15 +930,44 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         if (D > slot) return hipErrorIllegalState;   // records never exceed their chunks
         if ((e = hipMemcpyAsync(c->off.p, offh.data(), 8 * nc, hipMemcpyHostToDevice, c->s_main)) != hipSuccess)
             return e;
-        if (timing && (e = hipEventRecord(c->tevents[2], c->s_main)) != hipSuccess) return e;
-        if ((e = grid_for(c, T, K, kModeGather, nc, &grid)) != hipSuccess) return e;
-        if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2), grid, c->s_main)) != hipSuccess) return e;
-        if ((e = launch_pack(pj, true, pgrid, c->s_main)) != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[3], c->s_main)) != hipSuccess) return e;
-        // offh is pageable: the upload has completed once the stream has
+        // offh is pageable: wait for the upload before it goes out of scope
         if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return e;
-        reinterpret_cast<uint64_t*>(c->hsmall)[0] = D;
-        return hipEventRecord(ev[0], c->s_main);
+        if (!alloc_image(D)) return hipErrorOutOfMemory;
+        // piece boundaries: the first chunk at or past i * D / P of the payload
+        const uint64_t P = std::min<uint64_t>(kCodecPieces, nc);
+        std::vector<uint64_t> gb(P + 1, nc);
+        gb[0] = 0;
+        for (uint64_t i = 1; i < P; ++i)
+            gb[i] = std::max<uint64_t>(gb[i - 1], (uint64_t)(std::lower_bound(offh.begin(), offh.end(), D * i / P) -
+                                                             offh.begin()));
+        for (uint64_t i = 0; i < P; ++i) {
+            const uint64_t g0 = gb[i], g1 = gb[i + 1];
+            if (timing && (e = hipEventRecord(c->tevents[2 + 2 * i], c->s_main)) != hipSuccess) return e;
+            if (g1 > g0) {
+                j.g0 = g0;
+                j.g1 = g1;
+                pj.g0 = g0;
+                pj.g1 = g1;
+                if ((e = grid_for(c, T, K, kModeGather, g1 - g0, &grid)) != hipSuccess) return e;
+                if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2 + i), grid, c->s_main)) != hipSuccess)
+                    return e;
+                if ((e = launch_pack(pj, true, pack_grid(c, g1 - g0), c->s_main)) != hipSuccess) return e;
+            }
+            if (timing && (e = hipEventRecord(c->tevents[3 + 2 * i], c->s_main)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ev[i], c->s_main)) != hipSuccess) return e;
+            const uint64_t lo = g0 < nc ? offh[g0] : D, hi = g1 < nc ? offh[g1] : D;
+            if (hi > lo) {
+                hipStream_t cs = c->s_copy[i % ncs];
+                if (!t_link0) t_link0 = now_ns();
+                if ((e = hipStreamWaitEvent(cs, ev[i], 0)) != hipSuccess) return e;
+                if ((e = hipMemcpyAsync(himg + kHeader + tl + lo, c->staging.as<uint8_t>() + lo, hi - lo,
+                                        hipMemcpyDeviceToHost, cs)) != hipSuccess)
+                    return e;
+            }
+        }
+        codec_pieces = P;
+        *D_out = D;
+        return hipSuccess;
     };
     if (use_graph) {
         // ---- batched form: the whole device stage as one captured graph
@@ -1043,8 +1081,9 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         // a slot of its own (nslots >= 2): its slot-free event then belongs to
         // a copy that has already been issued.
         const bool ahead = nslots >= 2;
-        if (W) e = codec ? launch_codec() : two_pass ? launch_two_pass() : launch_window(0, 0);
-        for (uint64_t w = 0; w < W && e == hipSuccess; ++w) {
+        if (W && codec) e = launch_codec(&pos);
+        else if (W) e = two_pass ? launch_two_pass() : launch_window(0, 0);
+        for (uint64_t w = 0; w < W && e == hipSuccess && !codec; ++w) {
             if (w > 0 && !ahead) {
                 e = launch_window(w, pos);
                 if (e != hipSuccess) break;
@@ -1157,7 +1196,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         res->n_chunks = nc;
         res->link_bytes = D + tl + kHeader;
         res->ns_link = t_link0 ? t_link1 - t_link0 : 0;
-        res->ns_kernel = timing ? timed_ns(c, codec && W ? 2 : W) : 0;
+        res->ns_kernel = timing ? timed_ns(c, codec && W ? 1 + codec_pieces : W) : 0;
         res->ns_total = now_ns() - t_start;
         const uint8_t* kinds = himg + kHeader + len_a + rl_bytes;
         for (uint64_t i = 0; i < nc; ++i) {
@@ -1235,6 +1274,16 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     uint64_t slot;
     int nslots;
     pick_staging(c, o, nc, C, &slot, &nslots);
+    if (codec && !(o && o->window_bytes) && nc >= 2 * kCodecPieces) {
+        // codec images: kCodecPieces windows on a ring of up to three slots,
+        // so that each window's decode overlaps the next window's upload
+        const uint64_t s2 = ceil_div(nc, kCodecPieces) * C;
+        const int k = 3 * s2 <= c->budget ? 3 : 2 * s2 <= c->budget ? 2 : 0;
+        if (k) {
+            slot = s2;
+            nslots = k;
+        }
+    }
     std::vector<Window> wins;
     if (some) {
         // windows over the selected allocations' chunks only

@@ -122,6 +122,58 @@ def test_training_state_full_size():
 
 
 @pytest.mark.timeout(600)
+def test_training_state_codec_full_size():
+    """decoder-1.3B training state, seed 2, ~27 GB, 64 KiB chunks, dumped with
+    the byte-plane codec: header and tables of the codec layout, sampled
+    chunks' digests, kinds and payload records equal to the oracle's for the
+    same chunk, the payload length, and the whole state restored."""
+    torch.cuda.empty_cache()
+    _mem("start")
+    table = workloads.training_state("cuda", seed=2)
+    torch.cuda.synchronize()
+    sizes = [t.numel() * t.element_size() for _, t in table]
+    ctx = mk.ckpt_ctx_create(0, 64 << 30)
+    try:
+        opts = mk.make_opts(chunk_size=C, flags=mk.OPT_CODEC)
+        rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
+        assert rc == 0 and res.windows == 1, mk.ckpt_strerror(rc)
+        v = img.view()
+        (magic, ver, flags, c, n, nc, D, base, _, N, tcrc, hcrc) = struct.unpack_from("<8sIIIIQQIIQII",
+                                                                                     v[:64].tobytes())
+        assert flags == 2 and c == C and n == len(table) and N == sum(sizes)
+        tl = (32 * n + 9 * nc + 15) & ~15
+        assert v.size == 64 + tl + D
+        assert corc.crc32c(v[:60]) == hcrc and corc.crc32c(v[64:64 + tl]) == tcrc
+        crcs = np.frombuffer(v[64 + 32 * n:64 + 32 * n + 4 * nc].tobytes(), dtype=np.uint32)
+        rlen = np.frombuffer(v[64 + 32 * n + 4 * nc:64 + 32 * n + 8 * nc].tobytes(), dtype=np.uint32)
+        kinds = v[64 + 32 * n + 8 * nc:64 + 32 * n + 9 * nc]
+        assert int(rlen.astype(np.int64).sum()) == D and res.n_packed == int((kinds == 3).sum()) > 0
+        off = np.concatenate([[0], np.cumsum(rlen.astype(np.int64))[:-1]])
+        first = np.concatenate([[0], np.cumsum([(s + C - 1) // C for s in sizes])[:-1]]).astype(np.int64)
+        alloc_of = np.searchsorted(first, np.arange(nc), side="right") - 1
+        rng = np.random.default_rng(12)
+        pick = np.union1d(rng.choice(nc, size=300, replace=False), [0, nc - 1])
+        for g in pick:
+            a = int(alloc_of[g])
+            k = int(g - first[a])
+            buf = _bytes_of(table[a][1])
+            chunk = buf[k * C:min((k + 1) * C, sizes[a])].cpu().numpy()
+            assert corc.crc32c(chunk) == int(crcs[g]), g
+            rc, one = corc.dump([(1, chunk)], C, codec=True)
+            p1 = corc.parse(one)[1]
+            want_kind = int(one[64 + 32 + 8])              # the one chunk's kind
+            assert int(kinds[g]) == want_kind, g
+            rec = v[64 + tl + int(off[g]):64 + tl + int(off[g]) + int(rlen[g])]
+            assert int(rlen[g]) == p1["D"] and np.array_equal(rec, one[one.size - p1["D"]:]), g
+        print("codec payload %.3f of the logical bytes, %d of %d chunks packed"
+              % (D / N, res.n_packed, nc), flush=True)
+        _restore_equal(ctx, img, table, opts)
+        img.free()
+    finally:
+        mk.ckpt_ctx_destroy(ctx)
+
+
+@pytest.mark.timeout(600)
 def test_hpc_incremental_full_size():
     """HPC image, seed 3, 512 allocations, 40 GB, ~60 % zero chunks; 5 % of the
     chunks rewritten (seed 33); delta dump, then base restore + delta apply."""
