@@ -17,9 +17,12 @@
 // record replaces the chunk only when it is shorter than C. The image then
 // carries a u32 record-length table after the digest table.
 //
-// Work-group shape: 256 threads; lane t owns the C/4096 consecutive 16-byte
-// rows starting at row t*C/4096, so its elements of every plane are
-// consecutive and one block scan gives every lane its escape positions.
+// Work-group shape: 256 threads. In the encode and decode kernels lane t owns
+// the C/4096 consecutive 16-byte rows starting at row t*C/4096, so its
+// elements of every plane are consecutive: its codes and raw bytes are one
+// aligned piece of each section (written or read with whole 16-byte accesses
+// where they are that long) and one block scan gives every lane its escape
+// positions. Records are written and read in global memory directly.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,12 +39,15 @@ enum : uint32_t { kPlaneRaw = 0, kPlaneConst = 1, kPlaneDict = 2 };
 
 inline bool codec_chunk_supported(uint32_t C) { return C >= kCodecMinChunk && C <= kCodecMaxChunk; }
 
-// Constants of the decode kernel's digest for one chunk size.
+// Constants of the decode kernel's digest for one chunk size. A lane digests
+// its consecutive rows 16 bytes at a time: the running value is xored into
+// the first four bytes of the next row, whose raw CRC is the xor of
+// tab[i][byte i] over its 16 bytes.
 struct CodecConsts {
-    uint32_t table[256];   // r(byte b): raw CRC of one byte (one lookup per byte)
-    uint32_t lane[256];    // x^(8 (C/256) (255 - t)): moves lane t's segment digest
-                           // to its place in the chunk
-    uint32_t full_init;    // (~0) * x^(8C): the preset's term
+    uint32_t tab[16 * 256];   // tab[i][x] = r(byte x followed by 15 - i zero bytes)
+    uint32_t lane[256];       // x^(8 (C/256) (255 - t)): moves lane t's segment digest
+                              // to its place in the chunk
+    uint32_t full_init;       // (~0) * x^(8C): the preset's term
     uint32_t pad[63];
 };
 void build_codec_consts(CodecConsts* cc, uint32_t C);

@@ -67,17 +67,69 @@ __device__ inline uint32_t field16(uint64_t a, uint64_t b, int p) {
     return (uint32_t)(((p < 4 ? a : b) >> (16 * (p & 3))) & 0xFFFFu);
 }
 
+// NB bytes held in little-endian words w[] to p (global memory, aligned to
+// min(NB, 16)).
+template <int NB>
+__device__ inline void store_bytes(uint8_t* p, const uint32_t* w) {
+    if constexpr (NB == 1) {
+        *p = (uint8_t)w[0];
+    } else if constexpr (NB == 2) {
+        *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
+    } else if constexpr (NB == 4) {
+        *reinterpret_cast<uint32_t*>(p) = w[0];
+    } else if constexpr (NB == 8) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB / 16; ++i)
+            reinterpret_cast<uint4*>(p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+    }
+}
+
+template <int NB>
+__device__ inline void load_bytes(const uint8_t* p, uint32_t* w) {
+    if constexpr (NB == 1) {
+        w[0] = *p;
+    } else if constexpr (NB == 2) {
+        w[0] = *reinterpret_cast<const uint16_t*>(p);
+    } else if constexpr (NB == 4) {
+        w[0] = *reinterpret_cast<const uint32_t*>(p);
+    } else if constexpr (NB == 8) {
+        const uint2 x = *reinterpret_cast<const uint2*>(p);
+        w[0] = x.x;
+        w[1] = x.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB / 16; ++i) {
+            const uint4 x = reinterpret_cast<const uint4*>(p)[i];
+            w[4 * i] = x.x;
+            w[4 * i + 1] = x.y;
+            w[4 * i + 2] = x.z;
+            w[4 * i + 3] = x.w;
+        }
+    }
+}
+
+__device__ inline uint32_t byte_in(const uint32_t* w, int i) { return (w[i >> 2] >> (8 * (i & 3))) & 255u; }
+
 // Size pass (ENCODE false): the record length of every full DATA chunk; the
 // chunk becomes PACKED when it is shorter than C. Encode pass: the record of
-// every PACKED chunk, built in LDS and copied to its payload offset.
+// every PACKED chunk, written to its payload offset (every byte of the
+// record exactly once, padding included).
+// Byte counts go to kHistCopies histograms, lane l to copy l % kHistCopies:
+// the sign / exponent planes of floating-point data hold few distinct bytes,
+// and the lanes of a wave adding to the same counter are served one at a
+// time. The copies are kHistStride words apart, one bank off each other.
+constexpr int kHistCopies = 4;
+constexpr int kHistStride = 8 * 256 + 1;
+
 template <int K, bool ENCODE>
 __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
-    __shared__ uint32_t s_hist[8 * 256];
+    __shared__ uint32_t s_hist[kHistCopies * kHistStride];
     __shared__ uint8_t s_code[8 * 256];
-    __shared__ uint8_t s_dict[8 * 16];
-    __shared__ uint32_t s_mode[8], s_esc[8], s_nused[8], s_sec[9];
+    __shared__ __align__(16) uint8_t s_dict[8 * 16];
+    __shared__ uint32_t s_mode[8], s_esc[8], s_nused[8];
     __shared__ unsigned long long s_w[2 * NW];
-    __shared__ uint4 s_rec[ENCODE ? kCodecMaxChunk / 16 : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t C = j.C, L = C / 8;
     for (uint64_t g = j.g0 + blockIdx.x; g < j.g1; g += gridDim.x) {
@@ -95,16 +147,21 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
         } else {
             if (kd != kPacked) continue;
         }
-        const uint4* src = reinterpret_cast<const uint4*>(ad.ptr + k * C) + (uint32_t)tid * K;
+        const uint4* src = reinterpret_cast<const uint4*>(ad.ptr + k * C);
         uint4 v[K];
+        // the size pass only counts bytes: rows interleaved across lanes
+        // (coalesced); the encode pass needs each lane's rows consecutive
 #pragma unroll
-        for (int r = 0; r < K; ++r) v[r] = src[r];
-        for (int i = tid; i < 8 * 256; i += NT) s_hist[i] = 0;
+        for (int r = 0; r < K; ++r) v[r] = ENCODE ? src[tid * K + r] : src[r * NT + tid];
+        for (int i = tid; i < kHistCopies * kHistStride; i += NT) s_hist[i] = 0;
+        if (ENCODE)
+            for (int i = tid; i < 8 * 256; i += NT) s_code[i] = 15;
         __syncthreads();
+        uint32_t* hist = s_hist + (tid % kHistCopies) * kHistStride;
 #pragma unroll
         for (int r = 0; r < K; ++r)
 #pragma unroll
-            for (int b = 0; b < 16; ++b) atomicAdd(&s_hist[(b & 7) * 256 + byte_of(v[r], b)], 1u);
+            for (int b = 0; b < 16; ++b) atomicAdd(&hist[(b & 7) * 256 + byte_of(v[r], b)], 1u);
         __syncthreads();
         // dictionaries: wave w selects for planes w and w + 4, one value per
         // round (largest count, then smallest value: key = count << 8 | 255 - v)
@@ -115,7 +172,10 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t val = (uint32_t)lane + 64u * q;
-                key[q] = (s_hist[p * 256 + val] << 8) | (255u - val);
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int cp = 0; cp < kHistCopies; ++cp) cnt += s_hist[cp * kHistStride + p * 256 + val];
+                key[q] = (cnt << 8) | (255u - val);
             }
             uint32_t covered = 0, n = 0, first = 0;
             for (int i = 0; i < 15; ++i) {
@@ -147,118 +207,138 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
             }
         }
         __syncthreads();
+        uint32_t mode[8], esc[8], base[8];
+        uint32_t rl = kRecordHead;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {   // work-group-uniform: kept in scalar registers
+            mode[p] = __builtin_amdgcn_readfirstlane(s_mode[p]);
+            esc[p] = __builtin_amdgcn_readfirstlane(s_esc[p]);
+            base[p] = rl;
+            rl += section_len(L, mode[p], esc[p]);
+        }
         if constexpr (!ENCODE) {
             if (tid == 0) {
-                uint32_t at = kRecordHead;
-                for (int p = 0; p < 8; ++p) at += section_len(L, s_mode[p], s_esc[p]);
-                if (at < C) {
+                if (rl < C) {
                     j.kind[g] = kPacked;
-                    j.rlen[g] = at;
+                    j.rlen[g] = rl;
                 } else {
                     j.rlen[g] = C;
                 }
             }
         } else {
-            if (tid == 0) {
-                uint32_t at = kRecordHead;
-                for (int p = 0; p < 8; ++p) {
-                    s_sec[p] = at;
-                    at += section_len(L, s_mode[p], s_esc[p]);
-                }
-                s_sec[8] = at;
-            }
-            for (int i = tid; i < 8 * 256; i += NT) s_code[i] = 15;
-            __syncthreads();
-            const uint32_t rl = s_sec[8];
-            const bool ok = rl < C && rl == j.rlen[g];
             if (tid < 8 * 16) {
                 const int p = tid >> 4, i = tid & 15;
                 if (i < (int)s_nused[p]) s_code[p * 256 + s_dict[p * 16 + i]] = (uint8_t)i;
             }
-            if (ok)
-                for (uint32_t i = tid; i < rl / 16; i += NT) s_rec[i] = make_uint4(0, 0, 0, 0);
-            __syncthreads();
-            if (!ok) {
+            if (!(rl < C && rl == j.rlen[g])) {   // the same on every lane
                 if (tid == 0) atomicOr(j.err, 1u);
                 continue;
             }
-            uint8_t* rec8 = reinterpret_cast<uint8_t*>(s_rec);
-            // head, constant values and dictionaries
-            if (tid < 8) {
-                rec8[tid] = (uint8_t)s_mode[tid];
-                reinterpret_cast<uint32_t*>(rec8 + 8)[tid] = s_esc[tid];
-                if (s_mode[tid] == kPlaneConst) rec8[s_sec[tid]] = s_dict[tid * 16];
+            uint8_t* dst = j.slot + j.off[g];
+            const uint32_t esc_at = 16 + r16(L / 2);
+            // head (48 bytes), constant values, dictionaries, escape padding
+            if (tid < 3) {
+                uint32_t hw[4];
+                if (tid == 0) {
+                    hw[0] = mode[0] | (mode[1] << 8) | (mode[2] << 16) | (mode[3] << 24);
+                    hw[1] = mode[4] | (mode[5] << 8) | (mode[6] << 16) | (mode[7] << 24);
+                    hw[2] = esc[0];
+                    hw[3] = esc[1];
+                } else if (tid == 1) {
+                    hw[0] = esc[2];
+                    hw[1] = esc[3];
+                    hw[2] = esc[4];
+                    hw[3] = esc[5];
+                } else {
+                    hw[0] = esc[6];
+                    hw[1] = esc[7];
+                    hw[2] = 0;
+                    hw[3] = 0;
+                }
+                store_bytes<16>(dst + 16 * tid, hw);
             }
-            if (tid < 8 * 16) {
-                const int p = tid >> 4, i = tid & 15;
-                if (s_mode[p] == kPlaneDict) rec8[s_sec[p] + i] = s_dict[p * 16 + i];
-            }
-            uint32_t mode[8], base[8];
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                mode[p] = s_mode[p];
-                base[p] = s_sec[p];
+                if (tid == 8 + p && mode[p] == kPlaneConst) {
+                    const uint32_t w[4] = {s_dict[p * 16], 0, 0, 0};
+                    store_bytes<16>(dst + base[p], w);
+                }
+                if (tid == 16 + p && mode[p] == kPlaneDict) {
+                    const uint4 d = *reinterpret_cast<const uint4*>(&s_dict[p * 16]);
+                    const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+                    store_bytes<16>(dst + base[p], w);
+                }
+                if (tid == 24 + p && mode[p] == kPlaneDict)
+                    for (uint32_t b = esc[p]; b < r16(esc[p]); ++b) dst[base[p] + esc_at + b] = 0;
             }
+            __syncthreads();   // s_code complete
             // escape positions: per-lane counts, then a block scan
             uint64_t ca = 0, cb = 0;
 #pragma unroll
-            for (int r = 0; r < K; ++r)
+            for (int p = 0; p < 8; ++p)
+                if (mode[p] == kPlaneDict) {
+                    uint32_t n15 = 0;
 #pragma unroll
-                for (int p = 0; p < 8; ++p)
-                    if (mode[p] == kPlaneDict) {
-                        const uint32_t n15 = (s_code[p * 256 + byte_of(v[r], p)] == 15) +
-                                             (s_code[p * 256 + byte_of(v[r], p + 8)] == 15);
-                        if (p < 4) ca += (uint64_t)n15 << (16 * p);
-                        else cb += (uint64_t)n15 << (16 * (p - 4));
-                    }
+                    for (int r = 0; r < K; ++r)
+                        n15 += (s_code[p * 256 + byte_of(v[r], p)] == 15) + (s_code[p * 256 + byte_of(v[r], p + 8)] == 15);
+                    if (p < 4) ca += (uint64_t)n15 << (16 * p);
+                    else cb += (uint64_t)n15 << (16 * (p - 4));
+                }
             uint64_t ta, tb;
             block_scan2(ca, cb, s_w, ta, tb);
-            uint32_t pre[8];
+            const uint32_t row0 = (uint32_t)tid * K;
 #pragma unroll
-            for (int p = 0; p < 8; ++p) pre[p] = field16(ca, cb, p);
-            const uint32_t esc_at = 16 + r16(L / 2);
+            for (int p = 0; p < 8; ++p) {
+                if (mode[p] == kPlaneRaw) {
+                    // the lane's 2K plane bytes: element 2r, 2r+1 of each row
+                    uint32_t w[(2 * K + 3) / 4];
 #pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const uint32_t row = (uint32_t)tid * K + r;
+                    for (int i = 0; i < (2 * K + 3) / 4; ++i) w[i] = 0;
 #pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    const uint32_t b0 = byte_of(v[r], p), b1 = byte_of(v[r], p + 8);
-                    if (mode[p] == kPlaneRaw) {
-                        *reinterpret_cast<uint16_t*>(rec8 + base[p] + 2 * row) = (uint16_t)(b0 | (b1 << 8));
-                    } else if (mode[p] == kPlaneDict) {
+                    for (int r = 0; r < K; ++r)
+                        w[r >> 1] |= (byte_of(v[r], p) | (byte_of(v[r], p + 8) << 8)) << (16 * (r & 1));
+                    store_bytes<2 * K>(dst + base[p] + 2 * row0, w);
+                } else if (mode[p] == kPlaneDict) {
+                    uint32_t pre = field16(ca, cb, p);
+                    uint32_t w[(K + 3) / 4];
+#pragma unroll
+                    for (int i = 0; i < (K + 3) / 4; ++i) w[i] = 0;
+#pragma unroll
+                    for (int r = 0; r < K; ++r) {
+                        const uint32_t b0 = byte_of(v[r], p), b1 = byte_of(v[r], p + 8);
                         const uint32_t c0 = s_code[p * 256 + b0], c1 = s_code[p * 256 + b1];
-                        rec8[base[p] + 16 + row] = (uint8_t)(c0 | (c1 << 4));
-                        if (c0 == 15) rec8[base[p] + esc_at + pre[p]++] = (uint8_t)b0;
-                        if (c1 == 15) rec8[base[p] + esc_at + pre[p]++] = (uint8_t)b1;
+                        w[r >> 2] |= (c0 | (c1 << 4)) << (8 * (r & 3));
+                        if (c0 == 15) dst[base[p] + esc_at + pre++] = (uint8_t)b0;
+                        if (c1 == 15) dst[base[p] + esc_at + pre++] = (uint8_t)b1;
                     }
+                    store_bytes<K>(dst + base[p] + 16 + row0, w);
                 }
+                // one plane at a time: keeps the compiler from hoisting every
+                // plane's table lookups (hundreds of live registers)
+                asm volatile("" ::: "memory");
             }
-            __syncthreads();
-            uint4* dst = reinterpret_cast<uint4*>(j.slot + j.off[g]);
-            for (uint32_t i = tid; i < rl / 16; i += NT) dst[i] = s_rec[i];
         }
     }
 }
 
-// Decode of PACKED chunks: record to LDS, head checked, escape positions by a
-// block scan (their count checked against the head), rows decoded, stored to
-// the allocation and digested per lane (one table lookup per byte); the lane
-// digests are combined into the chunk's CRC and compared with the image's.
+// Decode of PACKED chunks from the staging window: head checked, escape
+// positions by a block scan (their count checked against the head), rows
+// decoded, stored to the allocation and digested per lane, 16 bytes per
+// step; the lane digests are combined into the chunk's CRC and compared
+// with the image's.
 template <int K>
 __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen, const CodecConsts* cc) {
-    __shared__ uint4 s_rec[kCodecMaxChunk / 16];
-    __shared__ uint32_t s_tab[256];
-    __shared__ uint32_t s_mode[8], s_esc[8], s_sec[9];
-    __shared__ uint32_t s_ok;
+    __shared__ uint32_t s_tab[16 * 256];
     __shared__ unsigned long long s_w[2 * NW];
     __shared__ uint32_t s_red[NW];
     const int tid = threadIdx.x;
-    for (int i = tid; i < 256; i += NT) s_tab[i] = cc->table[i];
+    for (int i = tid; i < 16 * 256; i += NT) s_tab[i] = cc->tab[i];
     const uint32_t lanec = cc->lane[tid], full_init = cc->full_init;
     const uint32_t C = jl.job[0].C, L = C / 8;
     const uint64_t total = jl.prefix[jl.n_jobs];
+    const uint32_t row0 = (uint32_t)tid * K;
     for (uint64_t tk = blockIdx.x; tk < total; tk += gridDim.x) {
-        __syncthreads();   // the previous chunk's LDS is no longer read
+        __syncthreads();   // s_tab loaded; s_w / s_red of the previous chunk read
         uint32_t jj = 0;
         while (jj + 1 < jl.n_jobs && jl.prefix[jj + 1] <= tk) ++jj;
         const ChunkJob& job = jl.job[jj];
@@ -273,45 +353,39 @@ __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen,
             if (tid == 0) atomicMin(job.bad, (unsigned long long)g);
             continue;
         }
-        const uint4* src = reinterpret_cast<const uint4*>(job.slot + (job.off[g] - job.slot_base));
-        for (uint32_t i = tid; i < rl / 16; i += NT) s_rec[i] = src[i];
-        __syncthreads();
-        const uint8_t* rec8 = reinterpret_cast<const uint8_t*>(s_rec);
-        if (tid == 0) {
-            const uint32_t* h32 = reinterpret_cast<const uint32_t*>(rec8);
-            bool ok = h32[10] == 0 && h32[11] == 0;
-            uint32_t at = kRecordHead;
-            for (int p = 0; p < 8; ++p) {
-                const uint32_t mode = rec8[p], esc = h32[2 + p];
-                ok = ok && mode <= kPlaneDict && (mode == kPlaneDict || esc == 0) && esc <= L;
-                s_mode[p] = mode;
-                s_esc[p] = esc;
-                s_sec[p] = at;
-                if (ok) at += section_len(L, mode, esc);
-            }
-            s_sec[8] = at;
-            s_ok = ok && at == rl;
+        const uint8_t* rec = job.slot + (job.off[g] - job.slot_base);
+        uint32_t h[12];
+        load_bytes<16>(rec, h);
+        load_bytes<16>(rec + 16, h + 4);
+        load_bytes<16>(rec + 32, h + 8);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) h[i] = __builtin_amdgcn_readfirstlane(h[i]);   // the same on every lane
+        uint32_t mode[8], esc[8], base[8];
+        bool ok = h[10] == 0 && h[11] == 0;
+        uint32_t at = kRecordHead;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            mode[p] = byte_in(h, p);
+            esc[p] = h[2 + p];
+            ok = ok && mode[p] <= kPlaneDict && (mode[p] == kPlaneDict || esc[p] == 0) && esc[p] <= L;
+            base[p] = at;
+            if (ok) at += section_len(L, mode[p], esc[p]);
         }
-        __syncthreads();
-        if (!s_ok) {
+        if (!(ok && at == rl)) {   // the same on every lane
             if (tid == 0) atomicMin(job.bad, (unsigned long long)g);
             continue;
         }
-        uint32_t mode[8], base[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            mode[p] = s_mode[p];
-            base[p] = s_sec[p];
-        }
-        const uint32_t row0 = (uint32_t)tid * K;
+        // codes of the lane's rows and their escape counts
+        uint32_t cw[8][(K + 3) / 4];
         uint64_t ca = 0, cb = 0;
 #pragma unroll
         for (int p = 0; p < 8; ++p)
             if (mode[p] == kPlaneDict) {
+                load_bytes<K>(rec + base[p] + 16 + row0, cw[p]);
                 uint32_t n15 = 0;
 #pragma unroll
                 for (int r = 0; r < K; ++r) {
-                    const uint32_t byte = rec8[base[p] + 16 + row0 + r];
+                    const uint32_t byte = byte_in(cw[p], r);
                     n15 += ((byte & 15u) == 15u) + ((byte >> 4) == 15u);
                 }
                 if (p < 4) ca += (uint64_t)n15 << (16 * p);
@@ -322,49 +396,66 @@ __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen,
         bool good = true;
 #pragma unroll
         for (int p = 0; p < 8; ++p)
-            if (mode[p] == kPlaneDict && field16(ta, tb, p) != s_esc[p]) good = false;
+            if (mode[p] == kPlaneDict && field16(ta, tb, p) != esc[p]) good = false;
         if (!good) {   // the same on every lane: totals are block-wide
             if (tid == 0) atomicMin(job.bad, (unsigned long long)g);
             continue;
         }
-        uint32_t pre[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) pre[p] = field16(ca, cb, p);
         const uint32_t esc_at = 16 + r16(L / 2);
-        uint4* dst = reinterpret_cast<uint4*>(ad.ptr + k * C);
+        uint32_t out[K][4];
+#pragma unroll
+        for (int r = 0; r < K; ++r) out[r][0] = out[r][1] = out[r][2] = out[r][3] = 0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int wl = p >> 2, sh = 8 * (p & 3);
+            if (mode[p] == kPlaneRaw) {
+                uint32_t w[(2 * K + 3) / 4];
+                load_bytes<2 * K>(rec + base[p] + 2 * row0, w);
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    out[r][wl] |= byte_in(w, 2 * r) << sh;
+                    out[r][2 + wl] |= byte_in(w, 2 * r + 1) << sh;
+                }
+            } else if (mode[p] == kPlaneConst) {
+                const uint32_t b = rec[base[p]];
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    out[r][wl] |= b << sh;
+                    out[r][2 + wl] |= b << sh;
+                }
+            } else {
+                uint32_t d[4];
+                load_bytes<16>(rec + base[p], d);
+                uint32_t pre = field16(ca, cb, p);
+                const uint8_t* escs = rec + base[p] + esc_at;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const uint32_t byte = byte_in(cw[p], r);
+                    const uint32_t c0 = byte & 15u, c1 = byte >> 4;
+                    const uint32_t b0 = c0 < 15 ? byte_in(d, c0) : escs[pre++];
+                    const uint32_t b1 = c1 < 15 ? byte_in(d, c1) : escs[pre++];
+                    out[r][wl] |= b0 << sh;
+                    out[r][2 + wl] |= b1 << sh;
+                }
+            }
+            asm volatile("" ::: "memory");   // one plane at a time (register pressure)
+        }
+        uint4* dst = reinterpret_cast<uint4*>(ad.ptr + k * C) + row0;
         uint32_t crc = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const uint32_t row = row0 + r;
-            uint32_t w[4] = {0, 0, 0, 0};
+            dst[r] = make_uint4(out[r][0], out[r][1], out[r][2], out[r][3]);
+            const uint32_t x[4] = {out[r][0] ^ crc, out[r][1], out[r][2], out[r][3]};
+            uint32_t c = 0;
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                uint32_t b0, b1;
-                if (mode[p] == kPlaneRaw) {
-                    b0 = rec8[base[p] + 2 * row];
-                    b1 = rec8[base[p] + 2 * row + 1];
-                } else if (mode[p] == kPlaneConst) {
-                    b0 = b1 = rec8[base[p]];
-                } else {
-                    const uint32_t byte = rec8[base[p] + 16 + row];
-                    const uint32_t c0 = byte & 15u, c1 = byte >> 4;
-                    b0 = c0 < 15 ? rec8[base[p] + c0] : rec8[base[p] + esc_at + pre[p]++];
-                    b1 = c1 < 15 ? rec8[base[p] + c1] : rec8[base[p] + esc_at + pre[p]++];
-                }
-                w[p >> 2] |= b0 << (8 * (p & 3));
-                w[2 + (p >> 2)] |= b1 << (8 * (p & 3));
-            }
-            dst[row] = make_uint4(w[0], w[1], w[2], w[3]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) crc = (crc >> 8) ^ s_tab[(crc ^ (w[q] >> (8 * b))) & 255u];
+            for (int i = 0; i < 16; ++i) c ^= s_tab[i * 256 + byte_in(x, i)];
+            crc = c;
         }
         // r(chunk) = xor over lanes of r(segment t) * x^(8 * bytes after it)
-        uint32_t x = gf_mul(crc, lanec);
+        uint32_t xr = gf_mul(crc, lanec);
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) x ^= __shfl_xor(x, m);
-        if ((tid & 63) == 0) s_red[tid >> 6] = x;
+        for (int m = 32; m >= 1; m >>= 1) xr ^= __shfl_xor(xr, m);
+        if ((tid & 63) == 0) s_red[tid >> 6] = xr;
         __syncthreads();
         if (tid == 0) {
             uint32_t raw = 0;
@@ -391,9 +482,9 @@ hipError_t unpack_k(const JobList& jl, const uint32_t* rlen, const CodecConsts* 
 
 void build_codec_consts(CodecConsts* cc, uint32_t C) {
     for (uint32_t b = 0; b < 256; ++b) {
-        uint32_t r = b;
+        uint32_t r = b;   // r(byte b): the register after one byte from 0
         for (int i = 0; i < 8; ++i) r = (r >> 1) ^ ((r & 1u) ? kPoly : 0u);
-        cc->table[b] = r;
+        for (int i = 0; i < 16; ++i) cc->tab[i * 256 + b] = gf_mul(r, xpow8(15 - i));
     }
     const uint64_t seg = C / kCodecThreads;   // bytes per lane
     for (int t = 0; t < kCodecThreads; ++t) cc->lane[t] = xpow8(seg * (uint64_t)(kCodecThreads - 1 - t));
