@@ -140,3 +140,61 @@ def test_image_save_load_round_trip(mklib, tmp_path):
     assert mklib.ckpt_image_load(str(tmp_path / "missing.img").encode(), 4, ctypes.byref(h3)) == -8
     assert mklib.ckpt_image_save(h, str(tmp_path / "no" / "dir.img").encode(), 2) == -8
     mklib.ckpt_image_free(h)
+
+
+def test_codec_images_import_and_merge_on_the_host(mklib):
+    """The library's host-side image handling of the codec layout: import
+    validates oracle-made codec images (and rejects table corruptions the
+    oracle rejects), and ckpt_merge of codec / plain bases and deltas is
+    byte-identical to the oracle's merge."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as corc
+    vp = ctypes.c_void_p
+    mklib.ckpt_image_import.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+    mklib.ckpt_image_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]
+    mklib.ckpt_image_free.argtypes = [vp]
+    mklib.ckpt_merge.argtypes = [vp, vp, ctypes.POINTER(vp)]
+
+    def imp(a):
+        h = vp()
+        rc = mklib.ckpt_image_import(a.ctypes.data, a.size, ctypes.byref(h))
+        return rc, h
+
+    def bytes_of(h):
+        p, n = vp(), ctypes.c_uint64()
+        assert mklib.ckpt_image_bytes(h, ctypes.byref(p), ctypes.byref(n)) == 0
+        return ctypes.string_at(p, n.value)
+
+    c = 4096
+    rng = np.random.default_rng(9)
+    bf16 = ((rng.standard_normal(20 * c) * 0.02).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    base = [(1, bf16.view(np.uint8).copy()),
+            (2, (rng.standard_normal(3 * c) * 1e-3).astype(np.float32).view(np.uint8)),
+            (3, rng.integers(0, 256, 2 * c + 7, dtype=np.uint8)),
+            (4, np.zeros(3 * c, np.uint8))]
+    new = [(i, a.copy()) for i, a in base]
+    new[0][1][3 * c:5 * c] = rng.integers(0, 256, 2 * c, dtype=np.uint8)
+    new[3][1][c:2 * c] = 9
+    for base_codec in (True, False):
+        rc, b = corc.dump(base, c, codec=base_codec)
+        rc, d = corc.dump(new, c, prev=b, codec=True)
+        rc, want = corc.merge(b, d)
+        assert rc == 0
+        rcb, hb = imp(b)
+        rcd, hd = imp(d)
+        assert rcb == 0 and rcd == 0
+        hm = vp()
+        assert mklib.ckpt_merge(hb, hd, ctypes.byref(hm)) == 0
+        assert bytes_of(hm) == want.tobytes()
+        for h in (hb, hd, hm):
+            mklib.ckpt_image_free(h)
+    # table corruptions of a codec image: a record length, a kind, the flag
+    rc, img = corc.dump(base, c, codec=True)
+    n, nc = 4, sum((a.size + c - 1) // c for _, a in base)
+    for pos in (64 + 32 * n + 4 * nc + 4, 64 + 32 * n + 8 * nc + 1, 12):
+        bad = img.copy()
+        bad[pos] ^= 0x04
+        want = corc.parse(bad)[0]
+        rc, h = imp(bad)
+        assert rc == want == -4, pos
