@@ -329,9 +329,11 @@ def ondemand(args, torch, mk, link):
 
 
 def storage(args, torch, mk, link):
-    """Storage leg on the training state (~27 GB): dump, then the image to a
-    file (synced); the file back into an image, then restore. Times each
-    part; the file is removed afterwards."""
+    """Storage leg on the training state (~27 GB). Sequential: dump, then the
+    image to a file (synced); the file back into an image, then restore.
+    Overlapped: ckpt_dump_file (the file written while the image is copied
+    out) and ckpt_restore_file (windows uploaded while the file loads).
+    Times each; the file is removed afterwards."""
     import os
     table = workloads.training_state("cuda", seed=2)
     torch.cuda.synchronize()
@@ -339,10 +341,11 @@ def storage(args, torch, mk, link):
     ctx = mk.ckpt_ctx_create(0, max(args.budget, N + (1 << 30)))
     opts = mk.make_opts(chunk_size=C)
     path = args.path
-    td, ts, tl, tr = [], [], [], []
+    t = {k: [] for k in ("dump", "save", "load", "restore", "dump_file", "restore_file")}
     size = 0
     try:
         for k in range(args.warmup + args.steps):
+            row = {}
             t0 = time.perf_counter()
             rc, img, _ = mk.ckpt_dump(ctx, table, opts=opts)
             t1 = time.perf_counter()
@@ -359,28 +362,43 @@ def storage(args, torch, mk, link):
             t4 = time.perf_counter()
             assert rc == 0, mk.ckpt_strerror(rc)
             img2.free()
+            os.remove(path)
+            row.update(dump=t1 - t0, save=t2 - t1, load=t3 - t2, restore=t4 - t3)
+            t0 = time.perf_counter()
+            rc, _, _ = mk.ckpt_dump_file(ctx, table, path, opts=opts, io_threads=args.io_threads)
+            t1 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            rc, _ = mk.ckpt_restore_file(ctx, path, table, opts=opts, io_threads=args.io_threads)
+            t2 = time.perf_counter()
+            assert rc == 0, mk.ckpt_strerror(rc)
+            os.remove(path)
+            row.update(dump_file=t1 - t0, restore_file=t2 - t1)
             if k >= args.warmup:
-                td.append(t1 - t0)
-                ts.append(t2 - t1)
-                tl.append(t3 - t2)
-                tr.append(t4 - t3)
-            _log("step %d: dump %.3f s, save %.3f s, load %.3f s, restore %.3f s" % (k, t1 - t0, t2 - t1, t3 - t2, t4 - t3))
+                for key, v in row.items():
+                    t[key].append(v)
+            _log("step %d: " % k + ", ".join("%s %.3f s" % (key, v) for key, v in row.items()))
     finally:
         if os.path.exists(path):
             os.remove(path)
         mk.ckpt_ctx_destroy(ctx)
-    md = lambda xs: _pct(xs, 50)
-    dump_save = md(td) + md(ts)
-    load_restore = md(tl) + md(tr)
+    md = {key: _pct(v, 50) for key, v in t.items()}
+    dump_save = md["dump"] + md["save"]
+    load_restore = md["load"] + md["restore"]
     return {
         "metric": "dump-to-file and restore-from-file GB/s at 1 GPU", "form": "storage",
-        "value": round(2 * N / (dump_save + load_restore) / 1e9, 3), "unit": "GB/s (logical, dump+save and load+restore)",
+        "value": round(2 * N / (md["dump_file"] + md["restore_file"]) / 1e9, 3),
+        "unit": "GB/s (logical, dump to file + restore from file, overlapped)",
         "config": {"workload": "decoder-1.3B training state (303 allocations)", "chunk": C, "N_bytes": N,
                    "image_bytes": size, "io_threads": args.io_threads, "path": path},
-        "dump_ms_p50": round(md(td) * 1e3, 1), "save_ms_p50": round(md(ts) * 1e3, 1),
-        "load_ms_p50": round(md(tl) * 1e3, 1), "restore_ms_p50": round(md(tr) * 1e3, 1),
-        "dump_and_save_GBps": round(N / dump_save / 1e9, 3), "load_and_restore_GBps": round(N / load_restore / 1e9, 3),
-        "file_write_GBps": round(size / md(ts) / 1e9, 3), "file_read_GBps": round(size / md(tl) / 1e9, 3),
+        "sequential": {"dump_ms_p50": round(md["dump"] * 1e3, 1), "save_ms_p50": round(md["save"] * 1e3, 1),
+                       "load_ms_p50": round(md["load"] * 1e3, 1), "restore_ms_p50": round(md["restore"] * 1e3, 1),
+                       "dump_and_save_GBps": round(N / dump_save / 1e9, 3),
+                       "load_and_restore_GBps": round(N / load_restore / 1e9, 3)},
+        "overlapped": {"dump_file_ms_p50": round(md["dump_file"] * 1e3, 1),
+                       "restore_file_ms_p50": round(md["restore_file"] * 1e3, 1),
+                       "dump_file_GBps": round(N / md["dump_file"] / 1e9, 3),
+                       "restore_file_GBps": round(N / md["restore_file"] / 1e9, 3)},
+        "file_write_GBps": round(size / md["save"] / 1e9, 3), "file_read_GBps": round(size / md["load"] / 1e9, 3),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
     }
 

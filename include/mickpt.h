@@ -210,6 +210,31 @@ void ckpt_image_free(ckpt_image* img);
  * opened, written, synced or read in full. */
 int  ckpt_image_save(const ckpt_image* img, const char* path, uint32_t threads);
 int  ckpt_image_load(const char* path, uint32_t threads, ckpt_image** out);
+/* Dump straight to a file, and restore straight from one, with the file I/O
+ * overlapping the host-link copies (the paper's checkpoint images live on
+ * storage, section 3.2; section 5.1 measures the write of the memory state
+ * to persistent storage and section 5.2 finds restores bounded also by
+ * loading checkpoint data from disk).
+ * ckpt_dump_file: as ckpt_dump, and the image is written to `path` (created
+ * or truncated) by `io_threads` threads (0 = 8) as the dump copies it out:
+ * every 64 MiB piece of the file goes to disk as soon as all its bytes are
+ * in host memory, the pieces holding the header and tables and the last one
+ * once the dump is done; the file is synced before the call returns. *out
+ * (may be NULL) receives the image, else it is freed. On any failure no
+ * image is returned and the file is removed; CKPT_EIO when the file cannot
+ * be written or synced, else the codes of ckpt_dump.
+ * ckpt_restore_file: as ckpt_restore of the image in `path`: the header and
+ * tables are read first and checked as in ckpt_restore, then `io_threads`
+ * threads (0 = 8) load the rest in 64 MiB pieces while the restore uploads
+ * each staging window once the file up to its end is loaded (without
+ * opts->window_bytes, eight windows on a ring of up to three slots).
+ * CKPT_EIO when the file cannot be read in full, else the codes of
+ * ckpt_restore. */
+int  ckpt_dump_file(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* prev, const char* path,
+                    uint32_t io_threads, const ckpt_opts* opts, void* stream, ckpt_result* res,
+                    ckpt_image** out);
+int  ckpt_restore_file(ckpt_ctx* ctx, const char* path, uint32_t io_threads, const ckpt_alloc_table* table,
+                       const ckpt_opts* opts, void* stream, ckpt_result* res);
 /* Static description of an error code. */
 const char* ckpt_strerror(int code);
 /* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes. */

@@ -146,6 +146,27 @@ struct ckpt_ctx {
 
 namespace mk {
 
+// Storage hooks. A dump told of a sink reports every payload copy into the
+// image as it is queued (segments of at most kSinkSegment bytes), so the
+// image can go to a file while the rest is still being copied; a restore
+// given a gate waits, before uploading each staging window, until the
+// image's bytes up to the window's end are in host memory.
+constexpr uint64_t kSinkSegment = 256ull << 20;
+struct PayloadSink {
+    virtual ~PayloadSink() = default;
+    virtual void begin(ckpt_image* im) = 0;                                    // before the first copy into im
+    virtual hipError_t issued(hipStream_t s, uint64_t lo, uint64_t hi) = 0;    // image bytes [lo, hi), queued on s
+    virtual void end() = 0;   // no more copies; returns once nothing of the sink reads the image
+};
+struct LoadGate {
+    virtual ~LoadGate() = default;
+    virtual bool wait(uint64_t hi) = 0;   // image bytes [0, hi) loaded; false when loading failed
+};
+int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+              const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink);
+int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                 void* stream, ckpt_result* res, bool some, LoadGate* gate);
+
 ckpt_image* image_new(uint64_t cap);
 void image_release(ckpt_image* im);   // returns the memory (pool or heap) and deletes im
 uint32_t next_epoch(ckpt_ctx* c, bool* wrapped);

@@ -603,8 +603,8 @@ void mk::digest_insert(ckpt_ctx* c, uint64_t uid, const uint32_t* crc_dev, uint6
 }
 
 // ------------------------------------------------------------ dump
-static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
-                     const ckpt_opts* o, void* stream, ckpt_result* res) {
+int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+              const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink) {
     const uint64_t t_start = now_ns();
     const uint32_t C = (o && o->chunk_size) ? o->chunk_size : kDefaultChunk;
     if (!valid_chunk(C)) return CKPT_EINVAL;
@@ -730,12 +730,26 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         im = image_new(kHeader + tl + upper);
         if (!im) return CKPT_ENOMEM;
         himg = im->p;
+        if (sink) sink->begin(im);
     }
+    // payload bytes [pay, pay + len) of the image from device memory, on
+    // stream s; with a sink, in segments it is told about one by one
+    auto copy_out = [&](uint64_t pay, const uint8_t* src, uint64_t len, hipStream_t s) -> hipError_t {
+        if (!sink) return hipMemcpyAsync(himg + kHeader + tl + pay, src, len, hipMemcpyDeviceToHost, s);
+        for (uint64_t d = 0; d < len; d += kSinkSegment) {
+            const uint64_t n = std::min<uint64_t>(kSinkSegment, len - d);
+            hipError_t e = hipMemcpyAsync(himg + kHeader + tl + pay + d, src + d, n, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = sink->issued(s, kHeader + tl + pay + d, kHeader + tl + pay + d + n);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     auto alloc_image = [&](uint64_t D) -> bool {
         if (im) return true;
         im = image_new(kHeader + tl + D);
         if (!im) return false;
         himg = im->p;
+        if (sink) sink->begin(im);
         return true;
     };
     uint64_t* hw = reinterpret_cast<uint64_t*>(c->hsmall);
@@ -747,6 +761,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         hipStreamSynchronize(c->s_main);
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
         (void)hipGetLastError();   // the error is reported by the return code
+        if (sink) sink->end();     // nothing reads the image after this
         if (im) image_release(im);
         if (e == hipErrorOutOfMemory) return CKPT_ENOMEM;
         if (res) res->hip_error = (int32_t)e;
@@ -960,9 +975,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
                 hipStream_t cs = c->s_copy[i % ncs];
                 if (!t_link0) t_link0 = now_ns();
                 if ((e = hipStreamWaitEvent(cs, ev[i], 0)) != hipSuccess) return e;
-                if ((e = hipMemcpyAsync(himg + kHeader + tl + lo, c->staging.as<uint8_t>() + lo, hi - lo,
-                                        hipMemcpyDeviceToHost, cs)) != hipSuccess)
-                    return e;
+                if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, hi - lo, cs)) != hipSuccess) return e;
             }
         }
         codec_pieces = P;
@@ -1071,9 +1084,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
         for (uint32_t i = 0; i < ncs && (uint64_t)i * piece < dw; ++i) {
             const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, dw - lo);
             if ((e = hipStreamWaitEvent(c->s_copy[i], ev[0], 0)) != hipSuccess) return fail(e);
-            if ((e = hipMemcpyAsync(himg + kHeader + tl + lo, c->staging.as<uint8_t>() + lo, len,
-                                    hipMemcpyDeviceToHost, c->s_copy[i])) != hipSuccess)
-                return fail(e);
+            if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, len, c->s_copy[i])) != hipSuccess) return fail(e);
         }
         pos = dw;
     } else {
@@ -1112,8 +1123,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             e = hipStreamWaitEvent(cs, ev[w], 0);
             if (e != hipSuccess) break;
             if (dw) {
-                e = hipMemcpyAsync(himg + kHeader + tl + pos, c->staging.as<uint8_t>() + (uint64_t)s * slot, dw,
-                                   hipMemcpyDeviceToHost, cs);
+                e = copy_out(pos, c->staging.as<uint8_t>() + (uint64_t)s * slot, dw, cs);
                 if (e != hipSuccess) break;
             }
             e = hipEventRecord(ev[W + s], cs);
@@ -1128,9 +1138,7 @@ static int dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_imag
             for (uint32_t i = 0; e == hipSuccess && i < ncs && (uint64_t)i * piece < pos; ++i) {
                 const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, pos - lo);
                 e = hipStreamWaitEvent(c->s_copy[i], ev[W - 1], 0);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(himg + kHeader + tl + lo, c->staging.as<uint8_t>() + lo, len,
-                                       hipMemcpyDeviceToHost, c->s_copy[i]);
+                if (e == hipSuccess) e = copy_out(lo, c->staging.as<uint8_t>() + lo, len, c->s_copy[i]);
             }
         }
         if (e != hipSuccess) return fail(e);
@@ -1217,7 +1225,7 @@ extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_
     *out = nullptr;
     if (!c || !table) return CKPT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    return dump_impl(c, table, prev, out, o, stream, res);
+    return dump_impl(c, table, prev, out, o, stream, res, nullptr);
 }
 
 // ------------------------------------------------------------ restore
@@ -1225,8 +1233,8 @@ extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_
 // (EMISMATCH otherwise). With `some` true it lists a subset of the image's
 // allocations by id, in any order (on-demand restore): only their chunks
 // are moved, verified and written; the others' memory is never touched.
-static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
-                        void* stream, ckpt_result* res, bool some) {
+int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                 void* stream, ckpt_result* res, bool some, LoadGate* gate) {
     const uint64_t t_start = now_ns();
     // CKPT_OPT_CODEC is accepted and has no effect: the image says how it is stored
     if (o && (o->reserved ||
@@ -1274,9 +1282,10 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
     uint64_t slot;
     int nslots;
     pick_staging(c, o, nc, C, &slot, &nslots);
-    if (codec && !(o && o->window_bytes) && nc >= 2 * kCodecPieces) {
-        // codec images: kCodecPieces windows on a ring of up to three slots,
-        // so that each window's decode overlaps the next window's upload
+    if ((codec || gate) && !(o && o->window_bytes) && nc >= 2 * kCodecPieces) {
+        // codec images and images still being loaded: kCodecPieces windows
+        // on a ring of up to three slots, so that each window's decode (or
+        // the load of its payload) overlaps the next window's upload
         const uint64_t s2 = ceil_div(nc, kCodecPieces) * C;
         const int k = 3 * s2 <= c->budget ? 3 : 2 * s2 <= c->budget ? 2 : 0;
         if (k) {
@@ -1578,6 +1587,12 @@ static int restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tab
         slot_used[s] = true;
         const uint64_t len = wend[w] - wbeg[w];
         if (len > slot) return CKPT_ECORRUPT;
+        if (gate && !gate->wait(kHeader + tl + wend[w])) {
+            // the image's file could not be read: let queued work finish
+            hipStreamSynchronize(c->s_main);
+            for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
+            return CKPT_EIO;
+        }
         if (len) HIPCHK(hipMemcpyAsync(sp, v.payload + wbeg[w], len, hipMemcpyHostToDevice, cs));
         HIPCHK(hipEventRecord(ev[w], cs));
         HIPCHK(hipStreamWaitEvent(c->s_main, ev[w], 0));
@@ -1661,7 +1676,7 @@ extern "C" int ckpt_restore(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc
     fill_result(res);
     if (!c || !img || !table) return CKPT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    return restore_impl(c, img, table, o, stream, res, false);
+    return restore_impl(c, img, table, o, stream, res, false, nullptr);
 }
 
 extern "C" int ckpt_restore_some(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table,
@@ -1669,7 +1684,7 @@ extern "C" int ckpt_restore_some(ckpt_ctx* c, const ckpt_image* img, const ckpt_
     fill_result(res);
     if (!c || !img || !table) return CKPT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    return restore_impl(c, img, table, o, stream, res, true);
+    return restore_impl(c, img, table, o, stream, res, true, nullptr);
 }
 
 // ------------------------------------------------------------ autotuner

@@ -109,6 +109,12 @@ def lib():
         L.ckpt_image_save.restype = ctypes.c_int
         L.ckpt_image_load.argtypes = [ctypes.c_char_p, _u32, ctypes.POINTER(vp)]
         L.ckpt_image_load.restype = ctypes.c_int
+        L.ckpt_dump_file.argtypes = [vp, ctypes.POINTER(ckpt_alloc_table), vp, ctypes.c_char_p, _u32,
+                                     ctypes.POINTER(ckpt_opts), vp, ctypes.POINTER(ckpt_result), ctypes.POINTER(vp)]
+        L.ckpt_dump_file.restype = ctypes.c_int
+        L.ckpt_restore_file.argtypes = [vp, ctypes.c_char_p, _u32, ctypes.POINTER(ckpt_alloc_table),
+                                        ctypes.POINTER(ckpt_opts), vp, ctypes.POINTER(ckpt_result)]
+        L.ckpt_restore_file.restype = ctypes.c_int
         L.ckpt_merge.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.ckpt_merge.restype = ctypes.c_int
         L.ckpt_image_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(_u64)]
@@ -294,6 +300,27 @@ def ckpt_image_load(path, threads=0):
     out = ctypes.c_void_p()
     rc = lib().ckpt_image_load(os.fsencode(path), int(threads), ctypes.byref(out))
     return rc, (Image(out.value) if rc == 0 else None)
+
+
+def ckpt_dump_file(ctx, table, path, prev=None, opts=None, stream=None, io_threads=0, keep_image=False):
+    """Dump with the image written to `path` while it is copied out:
+    (rc, Image or None, result); the image is returned only with keep_image."""
+    tab, keep = _table(table)
+    out = ctypes.c_void_p()
+    res = ckpt_result()
+    rc = lib().ckpt_dump_file(ctx, ctypes.byref(tab), prev.handle if prev is not None else None, os.fsencode(path),
+                              int(io_threads), ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                              ctypes.byref(res), ctypes.byref(out) if keep_image else None)
+    return rc, (Image(out.value) if rc == 0 and keep_image else None), res
+
+
+def ckpt_restore_file(ctx, path, table, opts=None, stream=None, io_threads=0):
+    """Restore the image in `path`, uploading windows as the file loads: (rc, result)."""
+    tab, keep = _table(table)
+    res = ckpt_result()
+    rc = lib().ckpt_restore_file(ctx, os.fsencode(path), int(io_threads), ctypes.byref(tab),
+                                 ctypes.byref(opts) if opts is not None else None, _stream(stream), ctypes.byref(res))
+    return rc, res
 
 
 def ckpt_merge(base, delta):
