@@ -140,6 +140,12 @@ struct ckpt_ctx {
     // pinned host scratch for small transfers
     uint8_t* hsmall = nullptr;
     uint64_t hsmall_cap = 0;
+    // pinned host scratch for per-chunk tables, and a second compute stream
+    // (codec dumps: encode on it while the main stream sizes later pieces)
+    uint8_t* hpin = nullptr;
+    uint64_t hpin_cap = 0;
+    hipStream_t s_aux = nullptr;
+    hipStream_t s_meta = nullptr;   // small host <-> device table transfers
     std::vector<hipEvent_t> events;
     std::vector<hipEvent_t> tevents;                      // timing events (begin, end) per launch
 };

@@ -326,6 +326,17 @@ hipError_t ensure_hsmall(ckpt_ctx* c, uint64_t n) {
     return e;
 }
 
+// Pinned host scratch for per-chunk tables (codec record lengths and offsets).
+hipError_t ensure_hpin(ckpt_ctx* c, uint64_t n) {
+    if (n <= c->hpin_cap) return hipSuccess;
+    if (c->hpin) (void)hipHostFree(c->hpin);
+    c->hpin = nullptr;
+    c->hpin_cap = 0;
+    hipError_t e = hipHostMalloc((void**)&c->hpin, n, hipHostMallocDefault);
+    if (e == hipSuccess) c->hpin_cap = n;
+    return e;
+}
+
 hipError_t ensure_tevents(ckpt_ctx* c, size_t n) {
     while (c->tevents.size() < n) {
         hipEvent_t e;
@@ -501,6 +512,12 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
         ge.dig.release();
     }
     if (c->hsmall) hipHostFree(c->hsmall);
+    if (c->hpin) (void)hipHostFree(c->hpin);
+    for (hipStream_t s : {c->s_aux, c->s_meta})
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
     delete c;
 }
 
@@ -682,14 +699,14 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     HIPCHK(c->status.ensure(8 * (max_win + 64)));
     const uint64_t W = wins.size();
     // ctl: tickets[max(W, 3, codec pieces + 2) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
-    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? kCodecPieces + 2 : 0);
+    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? 2 * kCodecPieces + 2 : 0);
     const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (n_tk + 1)),
                    ctl_err = ctl_wt + 8 * (W + 1), ctl_cnt = ctl_err + 16;
     HIPCHK(c->ctl.ensure(ctl_err + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
-    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, codec ? kCodecPieces + 1 : 0)));
+    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, codec ? 3 * kCodecPieces + 1 : 0)));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? kCodecPieces + 1 : 0)));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? 2 * kCodecPieces : 0)));
     const EngineConsts* ec;
     HIPCHK(get_consts(c, T, C, &ec));
 
@@ -759,6 +776,8 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     std::vector<bool> slot_used(nslots, false);
     auto fail = [&](hipError_t e) {
         hipStreamSynchronize(c->s_main);
+        if (c->s_aux) hipStreamSynchronize(c->s_aux);
+        if (c->s_meta) hipStreamSynchronize(c->s_meta);
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
         (void)hipGetLastError();   // the error is reported by the return code
         if (sink) sink->end();     // nothing reads the image after this
@@ -880,14 +899,19 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             return e;
         return hipEventRecord(ev[0], c->s_main);
     };
-    // Codec dump in one window: digests and kinds (classify), record lengths
-    // (size pass; DATA becomes PACKED where the record is shorter), payload
-    // offsets from a host prefix over the lengths; then in kCodecPieces
-    // pieces of about equal payload the DATA chunks are gathered and the
-    // PACKED records encoded, and each piece is copied out as soon as it is
-    // done, while the next one is encoded.
-    std::vector<uint32_t> rlen_host;
-    uint64_t codec_pieces = 0;
+    // Codec dump in one window, in kCodecPieces pieces of equal chunk
+    // counts. On the main stream, piece after piece: digests and kinds
+    // (classify) and record lengths (size pass; DATA becomes PACKED where the
+    // record is shorter). As each piece's size pass ends, a metadata stream
+    // brings its lengths to pinned host memory, the host extends the payload
+    // offsets over them and the stream takes the piece's offsets back up;
+    // then, on a second compute stream, the piece's DATA chunks are gathered
+    // and its PACKED records encoded, and its copy-out starts when that is
+    // done. The first copy-out so waits for one piece's passes, not for
+    // every chunk's. (Small copies return only once done, so they stay off
+    // the streams whose work the host queues ahead.)
+    uint32_t* rlen_h = nullptr;
+    uint64_t codec_pairs = 0;
     auto launch_codec = [&](uint64_t* D_out) -> hipError_t {
         hipError_t e;
         bool wrapped;
@@ -896,14 +920,19 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             return e;
         if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
         if ((e = c->rlen.ensure(4 * nc)) != hipSuccess) return e;
+        if ((e = ensure_hpin(c, 12 * nc)) != hipSuccess) return e;
+        if (!c->s_aux && (e = hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
+        if (!c->s_meta && (e = hipStreamCreateWithFlags(&c->s_meta, hipStreamNonBlocking)) != hipSuccess) return e;
+        uint64_t* off_h = reinterpret_cast<uint64_t*>(c->hpin);
+        rlen_h = reinterpret_cast<uint32_t*>(c->hpin + 8 * nc);
+        // the image at its upper bound (records never exceed their chunks)
+        if (!alloc_image(upper)) return hipErrorOutOfMemory;
         ChunkJob j;
         memset(&j, 0, sizeof(j));
         j.allocs = c->descs.as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
         j.amap = c->amap.as<uint32_t>();
-        j.g0 = 0;
-        j.g1 = nc;
         j.ec = ec;
         j.crc_out = crc_dev;
         j.kind_out = kind_dev;
@@ -918,67 +947,73 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         memset(&pj, 0, sizeof(pj));
         pj.allocs = c->descs.as<AllocDesc>();
         pj.amap = c->amap.as<uint32_t>();
-        pj.g0 = 0;
-        pj.g1 = nc;
         pj.C = C;
         pj.kind = kind_dev;
         pj.rlen = c->rlen.as<uint32_t>();
         pj.off = c->off.as<uint64_t>();
         pj.slot = c->staging.as<uint8_t>();
         pj.err = err;
-        int grid;
-        if ((e = grid_for(c, T, K, kModeClassify, nc, &grid)) != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[0], c->s_main)) != hipSuccess) return e;
-        if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 0), grid, c->s_main)) != hipSuccess) return e;
-        if ((e = launch_pack(pj, false, pack_grid(c, nc), c->s_main)) != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
-        rlen_host.resize(nc);
-        if ((e = hipMemcpyAsync(rlen_host.data(), c->rlen.p, 4 * nc, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
-            return e;
-        if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return e;
-        std::vector<uint64_t> offh(nc);
-        uint64_t D = 0;
-        for (uint64_t i = 0; i < nc; ++i) {
-            offh[i] = D;
-            D += rlen_host[i];
-        }
-        if (D > slot) return hipErrorIllegalState;   // records never exceed their chunks
-        if ((e = hipMemcpyAsync(c->off.p, offh.data(), 8 * nc, hipMemcpyHostToDevice, c->s_main)) != hipSuccess)
-            return e;
-        // offh is pageable: wait for the upload before it goes out of scope
-        if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return e;
-        if (!alloc_image(D)) return hipErrorOutOfMemory;
-        // piece boundaries: the first chunk at or past i * D / P of the payload
         const uint64_t P = std::min<uint64_t>(kCodecPieces, nc);
-        std::vector<uint64_t> gb(P + 1, nc);
-        gb[0] = 0;
-        for (uint64_t i = 1; i < P; ++i)
-            gb[i] = std::max<uint64_t>(gb[i - 1], (uint64_t)(std::lower_bound(offh.begin(), offh.end(), D * i / P) -
-                                                             offh.begin()));
+        std::vector<uint64_t> gb(P + 1);
+        for (uint64_t i = 0; i <= P; ++i) gb[i] = nc * i / P;
+        int grid;
         for (uint64_t i = 0; i < P; ++i) {
             const uint64_t g0 = gb[i], g1 = gb[i + 1];
-            if (timing && (e = hipEventRecord(c->tevents[2 + 2 * i], c->s_main)) != hipSuccess) return e;
+            j.g0 = pj.g0 = g0;
+            j.g1 = pj.g1 = g1;
+            if (timing && (e = hipEventRecord(c->tevents[2 * i], c->s_main)) != hipSuccess) return e;
             if (g1 > g0) {
-                j.g0 = g0;
-                j.g1 = g1;
-                pj.g0 = g0;
-                pj.g1 = g1;
-                if ((e = grid_for(c, T, K, kModeGather, g1 - g0, &grid)) != hipSuccess) return e;
-                if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2 + i), grid, c->s_main)) != hipSuccess)
+                if ((e = grid_for(c, T, K, kModeClassify, g1 - g0, &grid)) != hipSuccess) return e;
+                if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + i), grid, c->s_main)) != hipSuccess)
                     return e;
-                if ((e = launch_pack(pj, true, pack_grid(c, g1 - g0), c->s_main)) != hipSuccess) return e;
+                if ((e = launch_pack(pj, false, pack_grid(c, g1 - g0), c->s_main)) != hipSuccess) return e;
             }
-            if (timing && (e = hipEventRecord(c->tevents[3 + 2 * i], c->s_main)) != hipSuccess) return e;
+            if (timing && (e = hipEventRecord(c->tevents[2 * i + 1], c->s_main)) != hipSuccess) return e;
             if ((e = hipEventRecord(ev[i], c->s_main)) != hipSuccess) return e;
-            const uint64_t lo = g0 < nc ? offh[g0] : D, hi = g1 < nc ? offh[g1] : D;
-            if (hi > lo) {
-                hipStream_t cs = c->s_copy[i % ncs];
+        }
+        uint64_t D = 0;
+        for (uint64_t i = 0; i < P; ++i) {
+            const uint64_t g0 = gb[i], g1 = gb[i + 1];
+            if ((e = hipStreamWaitEvent(c->s_meta, ev[i], 0)) != hipSuccess) return e;
+            if (g1 > g0 && (e = hipMemcpyAsync(rlen_h + g0, pj.rlen + g0, 4 * (g1 - g0), hipMemcpyDeviceToHost,
+                                               c->s_meta)) != hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(c->s_meta)) != hipSuccess) return e;
+            const uint64_t lo = D;
+            for (uint64_t g = g0; g < g1; ++g) {
+                off_h[g] = D;
+                D += rlen_h[g];
+            }
+            if (D > upper || D > slot) return hipErrorIllegalState;   // records never exceed their chunks
+            if (g1 > g0 && (e = hipMemcpyAsync(c->off.as<uint64_t>() + g0, off_h + g0, 8 * (g1 - g0),
+                                               hipMemcpyHostToDevice, c->s_meta)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(ev[P + i], c->s_meta)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(c->s_aux, ev[P + i], 0)) != hipSuccess) return e;
+            if (timing && (e = hipEventRecord(c->tevents[2 * (P + i)], c->s_aux)) != hipSuccess) return e;
+            if (g1 > g0) {
+                j.g0 = pj.g0 = g0;
+                j.g1 = pj.g1 = g1;
+                if ((e = grid_for(c, T, K, kModeGather, g1 - g0, &grid)) != hipSuccess) return e;
+                if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + P + i), grid, c->s_aux)) != hipSuccess)
+                    return e;
+                if ((e = launch_pack(pj, true, pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess) return e;
+            }
+            if (timing && (e = hipEventRecord(c->tevents[2 * (P + i) + 1], c->s_aux)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ev[2 * P + i], c->s_aux)) != hipSuccess) return e;
+            if (D > lo) {
+                // one copy stream, pieces in order: two concurrent copies
+                // out reached 53 GB/s together against 57 for one
+                hipStream_t cs = c->s_copy[0];
                 if (!t_link0) t_link0 = now_ns();
-                if ((e = hipStreamWaitEvent(cs, ev[i], 0)) != hipSuccess) return e;
-                if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, hi - lo, cs)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(cs, ev[2 * P + i], 0)) != hipSuccess) return e;
+                if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, D - lo, cs)) != hipSuccess) return e;
             }
         }
-        codec_pieces = P;
+        // the main stream's later work (per-allocation digests, tables, the
+        // error flag) follows every encode
+        if (P && (e = hipStreamWaitEvent(c->s_main, ev[3 * P - 1], 0)) != hipSuccess) return e;
+        codec_pairs = 2 * P;
         *D_out = D;
         return hipSuccess;
     };
@@ -1163,7 +1198,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     // tables into the image
     if ((e = hipMemcpyAsync(himg + kHeader, c->arc.p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
         return fail(e);
-    if (codec) memcpy(himg + kHeader + len_a, rlen_host.data(), rl_bytes);   // little-endian host
+    if (codec) memcpy(himg + kHeader + len_a, rlen_h, rl_bytes);   // little-endian host
     if ((e = hipMemcpyAsync(himg + kHeader + len_a + rl_bytes, kind_dev, len_b, hipMemcpyDeviceToHost, c->s_main)) !=
         hipSuccess)
         return fail(e);
@@ -1177,7 +1212,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     // header
     const uint32_t sd = hdig[0];
     uint32_t tcrc = sd;
-    if (codec) tcrc = crc_combine(tcrc, host_crc32c(rlen_host.data(), rl_bytes), rl_bytes);
+    if (codec) tcrc = crc_combine(tcrc, host_crc32c(rlen_h, rl_bytes), rl_bytes);
     tcrc = crc_combine(tcrc, hdig[1], len_b);
     uint8_t* h = himg;
     memcpy(h, "MICKPT01", 8);
@@ -1204,7 +1239,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         res->n_chunks = nc;
         res->link_bytes = D + tl + kHeader;
         res->ns_link = t_link0 ? t_link1 - t_link0 : 0;
-        res->ns_kernel = timing ? timed_ns(c, codec && W ? 1 + codec_pieces : W) : 0;
+        res->ns_kernel = timing ? timed_ns(c, codec && W ? codec_pairs : W) : 0;
         res->ns_total = now_ns() - t_start;
         const uint8_t* kinds = himg + kHeader + len_a + rl_bytes;
         for (uint64_t i = 0; i < nc; ++i) {
