@@ -619,6 +619,10 @@ k_dump_stream(JobList jl) {
         cur = chunk_at<C>(jl, tk);
         stream(cur, last);
     }
+    // zero test of the current chunk already taken (and its aggregate
+    // published) in the previous iteration
+    bool known = false;
+    uint32_t any_known = 0;
     for (uint32_t it = 0;; ++it) {
         if (tk >= total) break;
         // the current chunk into registers (its streamed blocks have landed
@@ -651,7 +655,7 @@ k_dump_stream(JobList jl) {
         asm volatile("" : "+v"(lc), "+v"(ltid));
 
         // (LDS-only barriers from here on: streamed blocks stay in flight)
-        const uint32_t any = wg_any_lds<NW>(orw != 0, s_any);
+        const uint32_t any = known ? any_known : wg_any_lds<NW>(orw != 0, s_any);
         // When the kind does not depend on the digest -- a zero chunk, or no
         // previous digest for the allocation -- the payload length follows
         // from the zero test: its aggregate is published now, before the
@@ -660,7 +664,7 @@ k_dump_stream(JobList jl) {
         // digest: its status loads wait on the vector memory counter, which
         // by then the next chunk's loads have cleared.)
         const bool early = !any || job.prev_crc == nullptr || cur.prev_first == ~0ull;
-        if (!CLASSIFY && early && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
+        if (!CLASSIFY && early && !known && tid == 0) lb_publish(job.status, g - job.g0, any ? len16 : 0, job.epoch);
         ChunkAt nxt{};
         if (tk_next < total) {
             nxt = chunk_at<C>(jl, tk_next);
@@ -679,7 +683,28 @@ k_dump_stream(JobList jl) {
             job.crc_out[g] = crc;
             job.kind_out[g] = kd;
         }
+        known = false;
         if constexpr (!CLASSIFY) {
+            // the next chunk's blocks have had the digest's time to land: its
+            // zero test now, and its aggregate published before this chunk's
+            // look-back, so successors' look-backs pass it an iteration sooner
+            if (tk_next < total) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                uint32_t orn = 0;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const uint32_t o = r * R + 16u * tid;
+                    v4u x = r < K - 1 ? *reinterpret_cast<const v4u*>(s_buf + r * R + 16u * tid) : last;
+                    if (o + 16u > nxt.len) x = o < nxt.len ? load_partial(nxt.ptr + o, nxt.len - o) : vzero();
+                    orn |= or4(x);
+                }
+                any_known = wg_any_lds<NW>(orn != 0, s_any);
+                known = true;
+                const ChunkJob& jn = jl.job[nxt.jj];
+                const bool early_n = !any_known || jn.prev_crc == nullptr || nxt.prev_first == ~0ull;
+                if (early_n && tid == 0)
+                    lb_publish(jn.status, nxt.g - jn.g0, any_known ? ((nxt.len + 15u) & ~15u) : 0, jn.epoch);
+            }
             const uint64_t plen = kd == kData ? len16 : 0;
             if (tid < 64) {
                 const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
