@@ -19,12 +19,14 @@ hipcc "${FLAGS[@]}" -c "$SRC/serve.hip" -o "$BUILD/serve.o" &
 p4=$!
 hipcc "${FLAGS[@]}" -c "$SRC/codec.hip" -o "$BUILD/codec.o" &
 p6=$!
+hipcc "${FLAGS[@]}" -c "$SRC/gather.hip" -o "$BUILD/gather.o" &
+p7=$!
 hipcc -O2 -std=c++17 -fPIC -Wall -c "$SRC/hostmath.cpp" -o "$BUILD/hostmath.o" &
 p3=$!
 g++ -O2 -std=c++17 -fPIC -Wall -D__HIP_PLATFORM_AMD__ -I/opt/rocm/include -c "$SRC/storage.cpp" -o "$BUILD/storage.o" &
 p5=$!
-wait $p1; wait $p2; wait $p3; wait $p4; wait $p5; wait $p6
-hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/serve.o" "$BUILD/codec.o" \
+wait $p1; wait $p2; wait $p3; wait $p4; wait $p5; wait $p6; wait $p7
+hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUILD/runtime.o" "$BUILD/serve.o" "$BUILD/codec.o" "$BUILD/gather.o" \
     "$BUILD/hostmath.o" "$BUILD/storage.o" -lpthread
 mv "$OUT.tmp" "$OUT"
 echo "built $OUT"

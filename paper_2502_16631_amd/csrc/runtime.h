@@ -14,6 +14,7 @@
 
 #include "../../include/mickpt.h"
 #include "codec.h"
+#include "gather.h"
 #include "common.h"
 #include "kernels.h"
 

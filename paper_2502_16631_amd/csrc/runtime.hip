@@ -842,6 +842,21 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     // digest is done; its payload is small, so the extra read of D costs
     // little.
     const bool two_pass = prev != nullptr && W == 1 && !use_graph && nc > 0;
+    // the DATA chunks of [g0, g1) to their records at c->off (one window)
+    auto gather_job = [&](uint64_t g0, uint64_t g1) {
+        GatherJob gj;
+        memset(&gj, 0, sizeof(gj));
+        gj.allocs = c->descs.as<AllocDesc>();
+        gj.amap = c->amap.as<uint32_t>();
+        gj.g0 = g0;
+        gj.g1 = g1;
+        gj.C = C;
+        gj.kind = kind_dev;
+        gj.off = c->off.as<uint64_t>();
+        gj.slot = c->staging.as<uint8_t>();
+        gj.slot_base = 0;
+        return gj;
+    };
     auto launch_two_pass = [&]() -> hipError_t {
         hipError_t e;
         bool wrapped;
@@ -892,8 +907,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         const uint64_t tiles = ceil_div(nc, 256);
         if ((e = launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main)) != hipSuccess)
             return e;
-        if ((e = grid_for(c, T, K, kModeGather, nc, &grid)) != hipSuccess) return e;
-        if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + 2), grid, c->s_main)) != hipSuccess) return e;
+        if ((e = launch_gather(gather_job(0, nc), pack_grid(c, nc), c->s_main)) != hipSuccess) return e;
         if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(hw, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
             return e;
@@ -992,11 +1006,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             if ((e = hipStreamWaitEvent(c->s_aux, ev[P + i], 0)) != hipSuccess) return e;
             if (timing && (e = hipEventRecord(c->tevents[2 * (P + i)], c->s_aux)) != hipSuccess) return e;
             if (g1 > g0) {
-                j.g0 = pj.g0 = g0;
-                j.g1 = pj.g1 = g1;
-                if ((e = grid_for(c, T, K, kModeGather, g1 - g0, &grid)) != hipSuccess) return e;
-                if ((e = launch_chunks(T, K, kModeGather, one_job(j, tickets + P + i), grid, c->s_aux)) != hipSuccess)
-                    return e;
+                pj.g0 = g0;
+                pj.g1 = g1;
+                if ((e = launch_gather(gather_job(g0, g1), pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess) return e;
                 if ((e = launch_pack(pj, true, pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess) return e;
             }
             if (timing && (e = hipEventRecord(c->tevents[2 * (P + i) + 1], c->s_aux)) != hipSuccess) return e;
