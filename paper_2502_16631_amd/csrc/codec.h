@@ -26,6 +26,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "codec_consts.h"
 #include "kernels.h"
 
 namespace mk {
@@ -39,18 +40,7 @@ enum : uint32_t { kPlaneRaw = 0, kPlaneConst = 1, kPlaneDict = 2 };
 
 inline bool codec_chunk_supported(uint32_t C) { return C >= kCodecMinChunk && C <= kCodecMaxChunk; }
 
-// Constants of the decode kernel's digest for one chunk size. A lane digests
-// its consecutive rows 16 bytes at a time: the running value is xored into
-// the first four bytes of the next row, whose raw CRC is the xor of
-// tab[i][byte i] over its 16 bytes.
-struct CodecConsts {
-    uint32_t tab[16 * 256];   // tab[i][x] = r(byte x followed by 15 - i zero bytes)
-    uint32_t lane[256];       // x^(8 (C/256) (255 - t)): moves lane t's segment digest
-                              // to its place in the chunk
-    uint32_t full_init;       // (~0) * x^(8C): the preset's term
-    uint32_t pad[63];
-};
-void build_codec_consts(CodecConsts* cc, uint32_t C);
+// Constants of the decode kernel's digest: CodecConsts (codec_consts.h).
 
 // Size and encode passes over the chunks [g0, g1) of one table.
 struct PackJob {

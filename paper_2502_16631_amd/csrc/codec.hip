@@ -480,18 +480,6 @@ hipError_t unpack_k(const JobList& jl, const uint32_t* rlen, const CodecConsts* 
 
 }  // namespace
 
-void build_codec_consts(CodecConsts* cc, uint32_t C) {
-    for (uint32_t b = 0; b < 256; ++b) {
-        uint32_t r = b;   // r(byte b): the register after one byte from 0
-        for (int i = 0; i < 8; ++i) r = (r >> 1) ^ ((r & 1u) ? kPoly : 0u);
-        for (int i = 0; i < 16; ++i) cc->tab[i * 256 + b] = gf_mul(r, xpow8(15 - i));
-    }
-    const uint64_t seg = C / kCodecThreads;   // bytes per lane
-    for (int t = 0; t < kCodecThreads; ++t) cc->lane[t] = xpow8(seg * (uint64_t)(kCodecThreads - 1 - t));
-    cc->full_init = gf_mul(0xFFFFFFFFu, xpow8(C));
-    for (uint32_t& x : cc->pad) x = 0;
-}
-
 hipError_t launch_pack(const PackJob& j, bool encode, int grid, hipStream_t s) {
     if (!codec_chunk_supported(j.C) || !j.amap || grid < 1) return hipErrorInvalidValue;
     if (j.g1 <= j.g0) return hipSuccess;

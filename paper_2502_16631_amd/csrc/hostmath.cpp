@@ -1,5 +1,6 @@
 // Host arithmetic: see hostmath.h.
 #include "hostmath.h"
+#include "codec_consts.h"
 
 #include <nmmintrin.h>
 #include <string.h>
@@ -99,6 +100,18 @@ void build_engine_consts(EngineConsts* ec, int T, uint32_t C) {
         ec->x2n[i] = p;
         p = gf_mul(p, p);
     }
+}
+
+void build_codec_consts(CodecConsts* cc, uint32_t C) {
+    for (uint32_t b = 0; b < 256; ++b) {
+        uint32_t r = b;   // r(byte b): the register after one byte from 0
+        for (int i = 0; i < 8; ++i) r = (r >> 1) ^ ((r & 1u) ? kPoly : 0u);
+        for (int i = 0; i < 16; ++i) cc->tab[i * 256 + b] = gf_mul(r, xpow8(15 - i));
+    }
+    const uint64_t seg = C / 256;   // bytes per lane
+    for (int t = 0; t < 256; ++t) cc->lane[t] = xpow8(seg * (uint64_t)(255 - t));
+    cc->full_init = gf_mul(0xFFFFFFFFu, xpow8(C));
+    for (uint32_t& x : cc->pad) x = 0;
 }
 
 }  // namespace mk

@@ -1,5 +1,6 @@
-// CPU emulation of the GPU chunk engine's CRC decomposition, for testing
-// the engine constants on a machine without a GPU. It reproduces the
+// CPU emulation of the GPU chunk engine's CRC decomposition (and of the
+// codec decode kernel's), for testing the constants on a machine without a
+// GPU. It reproduces the
 // per-lane interleaved streams, the fold of the running digest into the
 // next block, the lane alignment, the tail
 // correction and the per-allocation combine exactly as the kernels do, using
@@ -8,6 +9,7 @@
 #include <string.h>
 #include <vector>
 
+#include "codec_consts.h"
 #include "common.h"
 #include "hostmath.h"
 
@@ -64,3 +66,26 @@ extern "C" uint32_t emu_alloc_crc(const uint32_t* crcs, uint64_t size, uint32_t 
 }
 
 extern "C" uint32_t emu_combine(uint32_t a, uint32_t b, uint64_t len_b) { return crc_combine(a, b, len_b); }
+
+// the codec decode kernel's digest of a full chunk of C bytes: 256 lanes,
+// lane t over its C/256 consecutive bytes 16 at a time (running value folded
+// into the next row), lane digests moved into place and xored, preset term
+extern "C" uint32_t emu_codec_crc(const uint8_t* p, uint32_t C) {
+    static CodecConsts cc;
+    build_codec_consts(&cc, C);
+    const uint32_t seg = C / 256;
+    uint32_t raw = 0;
+    for (int t = 0; t < 256; ++t) {
+        uint32_t crc = 0;
+        for (uint32_t r = 0; r < seg / 16; ++r) {
+            uint8_t b[16];
+            memcpy(b, p + (uint64_t)t * seg + 16u * r, 16);
+            for (int j = 0; j < 4; ++j) b[j] ^= (uint8_t)(crc >> (8 * j));
+            uint32_t c = 0;
+            for (int i = 0; i < 16; ++i) c ^= cc.tab[i * 256 + b[i]];
+            crc = c;
+        }
+        raw ^= gf_mul(crc, cc.lane[t]);
+    }
+    return ~(raw ^ cc.full_init);
+}

@@ -60,6 +60,8 @@ def emu():
     L.emu_alloc_crc.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
     L.emu_combine.restype = ctypes.c_uint32
     L.emu_combine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
+    L.emu_codec_crc.restype = ctypes.c_uint32
+    L.emu_codec_crc.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     return L
 
 
@@ -77,6 +79,17 @@ def test_engine_decomposition_equals_crc32c(emu, c, t, k):
             continue
         data = rng.integers(0, 256, ln, dtype=np.uint8)
         assert emu.emu_chunk_crc(data.ctypes.data, ln, c, t, k) == hw_crc32c(data), (c, t, k, ln)
+
+
+@pytest.mark.parametrize("c", [4096, 8192, 16384, 32768, 65536])
+def test_codec_decode_digest_equals_crc32c(emu, c):
+    """The codec decode kernel's digest (per-lane slice-by-16 over consecutive
+    rows, lane constants, preset term; the library's own constant builder)
+    is CRC-32C: checked against the hardware instruction."""
+    rng = np.random.default_rng(c)
+    for data in (rng.integers(0, 256, c, dtype=np.uint8), np.zeros(c, np.uint8),
+                 (rng.standard_normal(c // 4) * 0.02).astype(np.float32).view(np.uint8)):
+        assert emu.emu_codec_crc(data.ctypes.data, c) == hw_crc32c(data), c
 
 
 def test_combine_reproduces_whole_allocation_crc(emu):
