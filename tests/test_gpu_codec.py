@@ -212,3 +212,44 @@ def test_codec_option_errors(ctx):
     # the context still works afterwards
     img, _, _ = codec_parity(ctx, table, 4096)
     restore_check(ctx, img, table)
+
+
+def test_served_loop_rejects_codec_images_and_takes_plain_ones(ctx):
+    """The served request loop restores the plain layout only: a codec image
+    ends with CKPT_EINVAL, the plain image of the same state restores, and a
+    served delta dump against a codec base gives the oracle's plain delta."""
+    import time
+    c = 65536
+    table = typed_table(c, seed=45)
+    img, oimg, _ = codec_parity(ctx, table, c)
+    rc, plain, _ = mk.ckpt_dump(ctx, table, opts=mk.make_opts(chunk_size=c))
+    assert rc == 0
+    srv = mk.ckpt_serve_create(ctx, 4, 1 << 30)
+    try:
+        targets = [(i, torch.zeros_like(t)) for i, t in table]
+        rc1, t1 = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, targets, img=img)
+        rc2, t2 = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, targets, img=plain)
+        new = [(i, t.clone()) for i, t in table]
+        workloads.mutate_runs(new, seed=46, chunk=c, frac=0.3, run_mean=2)
+        rc3, t3 = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, new, prev=img)
+        assert rc1 == rc2 == rc3 == 0
+        got = {}
+        t0 = time.time()
+        while len(got) < 3:
+            for k, tk in (("codec", t1), ("plain", t2), ("delta", t3)):
+                if k not in got:
+                    done, rc, out, lat = mk.ckpt_serve_poll(srv, tk)
+                    if done:
+                        got[k] = (rc, out)
+            assert time.time() - t0 < 120, "serving requests did not complete"
+            time.sleep(0.001)
+        assert got["codec"][0] == mk.CKPT_EINVAL
+        assert got["plain"][0] == 0
+        torch.cuda.synchronize()
+        for (_, a), (_, b) in zip(table, targets):
+            assert torch.equal(a, b)
+        assert got["delta"][0] == 0
+        rc, want = corc.dump(workloads.host_copy(new), c, prev=oimg)
+        assert rc == 0 and np.array_equal(got["delta"][1].view(), want)
+    finally:
+        mk.ckpt_serve_destroy(srv)
