@@ -92,10 +92,9 @@ typedef struct ckpt_image ckpt_image;   /* an image in host memory (pinned if av
  * (section 7); the codec is this library's: 8 byte planes per chunk, each
  * stored as one value, as 4-bit codes into a 15-entry dictionary of its most
  * frequent bytes plus escaped bytes, or raw. It needs 4096 <= chunk_size <=
- * 65536, no CKPT_OPT_PER_ALLOC or CKPT_OPT_GRAPH (CKPT_EINVAL otherwise),
- * and a staging budget that holds the whole payload in one window
- * (CKPT_ENOMEM otherwise). Restoring PACKED records needs the same chunk
- * sizes (CKPT_EINVAL otherwise). */
+ * 65536 and no CKPT_OPT_PER_ALLOC or CKPT_OPT_GRAPH (CKPT_EINVAL
+ * otherwise). Restoring PACKED records needs the same chunk sizes
+ * (CKPT_EINVAL otherwise). */
 #define CKPT_OPT_CODEC      8u
 typedef struct {
     uint32_t chunk_size;     /* bytes per chunk; 0 = 65536                                   */

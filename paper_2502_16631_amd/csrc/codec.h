@@ -52,7 +52,8 @@ struct PackJob {
     uint8_t* kind;           // size: DATA becomes PACKED where the record is shorter
     uint32_t* rlen;          // size: record length of every chunk (written); encode: read
     const uint64_t* off;     // encode: payload offset of chunk g in slot
-    uint8_t* slot;           // encode: the payload (offset 0)
+    uint8_t* slot;           // encode: staging holding the payload from offset slot_base
+    uint64_t slot_base;
     uint32_t* err;           // encode: set when a record's length differs from the size pass
 };
 

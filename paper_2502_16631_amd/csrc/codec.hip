@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
                 if (tid == 0) atomicOr(j.err, 1u);
                 continue;
             }
-            uint8_t* dst = j.slot + j.off[g];
+            uint8_t* dst = j.slot + (j.off[g] - j.slot_base);
             const uint32_t esc_at = 16 + r16(L / 2);
             // head (48 bytes), constant values, dictionaries, escape padding
             if (tid < 3) {

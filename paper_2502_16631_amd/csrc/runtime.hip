@@ -682,9 +682,6 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
     const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
     if ((uint64_t)nslots * slot > c->budget && nslots > 1) return CKPT_ENOMEM;
-    // the codec's payload offsets follow from the record lengths of the whole
-    // table: its image has to fit one staging window
-    if (codec && wins.size() > 1) return CKPT_ENOMEM;
 
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(ensure_copy_streams(c, ncs));
@@ -699,14 +696,15 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     HIPCHK(c->status.ensure(8 * (max_win + 64)));
     const uint64_t W = wins.size();
     // ctl: tickets[max(W, 3, codec pieces + 2) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
-    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? 2 * kCodecPieces + 2 : 0);
+    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? 2 * kCodecPieces + 2 : 0) + 1;
     const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (n_tk + 1)),
                    ctl_err = ctl_wt + 8 * (W + 1), ctl_cnt = ctl_err + 16;
     HIPCHK(c->ctl.ensure(ctl_err + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
-    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, codec ? 3 * kCodecPieces + 1 : 0)));
+    const uint64_t codec_p = codec ? (W == 1 ? std::min<uint64_t>(kCodecPieces, nc) : W) : 0;   // codec pieces
+    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, 4 * codec_p + 1)));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, codec ? 2 * kCodecPieces : 0)));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, 2 * codec_p)));
     const EngineConsts* ec;
     HIPCHK(get_consts(c, T, C, &ec));
 
@@ -842,8 +840,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     // digest is done; its payload is small, so the extra read of D costs
     // little.
     const bool two_pass = prev != nullptr && W == 1 && !use_graph && nc > 0;
-    // the DATA chunks of [g0, g1) to their records at c->off (one window)
-    auto gather_job = [&](uint64_t g0, uint64_t g1) {
+    // the DATA chunks of [g0, g1) to their records at c->off, in staging
+    // from sp on, which holds the payload from offset base
+    auto gather_job = [&](uint64_t g0, uint64_t g1, uint8_t* sp, uint64_t base) {
         GatherJob gj;
         memset(&gj, 0, sizeof(gj));
         gj.allocs = c->descs.as<AllocDesc>();
@@ -853,8 +852,8 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         gj.C = C;
         gj.kind = kind_dev;
         gj.off = c->off.as<uint64_t>();
-        gj.slot = c->staging.as<uint8_t>();
-        gj.slot_base = 0;
+        gj.slot = sp;
+        gj.slot_base = base;
         return gj;
     };
     auto launch_two_pass = [&]() -> hipError_t {
@@ -907,14 +906,18 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         const uint64_t tiles = ceil_div(nc, 256);
         if ((e = launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main)) != hipSuccess)
             return e;
-        if ((e = launch_gather(gather_job(0, nc), pack_grid(c, nc), c->s_main)) != hipSuccess) return e;
+        if ((e = launch_gather(gather_job(0, nc, c->staging.as<uint8_t>(), 0), pack_grid(c, nc), c->s_main)) !=
+            hipSuccess)
+            return e;
         if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(hw, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
             return e;
         return hipEventRecord(ev[0], c->s_main);
     };
-    // Codec dump in one window, in kCodecPieces pieces of equal chunk
-    // counts. On the main stream, piece after piece: digests and kinds
+    // Codec dump in pieces: in one window kCodecPieces pieces of equal chunk
+    // counts, else one piece per staging window (on the slot ring; a piece
+    // is encoded into its slot once the piece that used it before has been
+    // copied out). On the main stream, piece after piece: digests and kinds
     // (classify) and record lengths (size pass; DATA becomes PACKED where the
     // record is shorter). As each piece's size pass ends, a metadata stream
     // brings its lengths to pinned host memory, the host extends the payload
@@ -967,9 +970,10 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         pj.off = c->off.as<uint64_t>();
         pj.slot = c->staging.as<uint8_t>();
         pj.err = err;
-        const uint64_t P = std::min<uint64_t>(kCodecPieces, nc);
+        const bool one = W == 1;
+        const uint64_t P = codec_p;
         std::vector<uint64_t> gb(P + 1);
-        for (uint64_t i = 0; i <= P; ++i) gb[i] = nc * i / P;
+        for (uint64_t i = 0; i <= P; ++i) gb[i] = one ? nc * i / P : (i < P ? wins[i].g0 : nc);
         int grid;
         for (uint64_t i = 0; i < P; ++i) {
             const uint64_t g0 = gb[i], g1 = gb[i + 1];
@@ -998,17 +1002,26 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
                 off_h[g] = D;
                 D += rlen_h[g];
             }
-            if (D > upper || D > slot) return hipErrorIllegalState;   // records never exceed their chunks
+            // records never exceed their chunks (nor a window its slot)
+            if (D > upper || (one ? D : D - lo) > slot) return hipErrorIllegalState;
+            uint8_t* sp = c->staging.as<uint8_t>() + (one ? 0 : (i % nslots) * slot);
+            const uint64_t base = one ? 0 : lo;
             if (g1 > g0 && (e = hipMemcpyAsync(c->off.as<uint64_t>() + g0, off_h + g0, 8 * (g1 - g0),
                                                hipMemcpyHostToDevice, c->s_meta)) != hipSuccess)
                 return e;
             if ((e = hipEventRecord(ev[P + i], c->s_meta)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(c->s_aux, ev[P + i], 0)) != hipSuccess) return e;
+            // the slot's previous piece is copied out
+            if (!one && i >= (uint64_t)nslots && (e = hipStreamWaitEvent(c->s_aux, ev[3 * P + i - nslots], 0)) != hipSuccess)
+                return e;
             if (timing && (e = hipEventRecord(c->tevents[2 * (P + i)], c->s_aux)) != hipSuccess) return e;
             if (g1 > g0) {
                 pj.g0 = g0;
                 pj.g1 = g1;
-                if ((e = launch_gather(gather_job(g0, g1), pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess) return e;
+                pj.slot = sp;
+                pj.slot_base = base;
+                if ((e = launch_gather(gather_job(g0, g1, sp, base), pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess)
+                    return e;
                 if ((e = launch_pack(pj, true, pack_grid(c, g1 - g0), c->s_aux)) != hipSuccess) return e;
             }
             if (timing && (e = hipEventRecord(c->tevents[2 * (P + i) + 1], c->s_aux)) != hipSuccess) return e;
@@ -1019,8 +1032,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
                 hipStream_t cs = c->s_copy[0];
                 if (!t_link0) t_link0 = now_ns();
                 if ((e = hipStreamWaitEvent(cs, ev[2 * P + i], 0)) != hipSuccess) return e;
-                if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, D - lo, cs)) != hipSuccess) return e;
+                if ((e = copy_out(lo, sp + (lo - base), D - lo, cs)) != hipSuccess) return e;
             }
+            if ((e = hipEventRecord(ev[3 * P + i], c->s_copy[0])) != hipSuccess) return e;
         }
         // the main stream's later work (per-allocation digests, tables, the
         // error flag) follows every encode

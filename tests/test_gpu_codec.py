@@ -205,13 +205,24 @@ def test_codec_option_errors(ctx):
                dict(chunk_size=4096, flags=mk.OPT_CODEC | mk.OPT_GRAPH)):
         rc, img, _ = mk.ckpt_dump(ctx, table, opts=mk.make_opts(**kw))
         assert rc == mk.CKPT_EINVAL and img is None, kw
-    # the payload has to fit one staging window
-    rc, img, _ = mk.ckpt_dump(ctx, table, opts=mk.make_opts(chunk_size=4096, flags=mk.OPT_CODEC,
-                                                          window_bytes=4 * 4096))
-    assert rc == mk.CKPT_ENOMEM and img is None
     # the context still works afterwards
     img, _, _ = codec_parity(ctx, table, 4096)
     restore_check(ctx, img, table)
+
+
+@pytest.mark.parametrize("c,win_chunks", [(4096, 4), (16384, 7), (65536, 3)])
+def test_codec_dump_over_several_staging_windows(ctx, c, win_chunks):
+    """A codec dump whose payload spans several staging windows (pieces on
+    the slot ring) gives the oracle's image, also as a delta and with
+    three slots; it restores."""
+    table = typed_table(c, seed=c + 7)
+    img, oimg, res = codec_parity(ctx, table, c, window_bytes=win_chunks * c)
+    assert res.windows > 2
+    codec_parity(ctx, table, c, window_bytes=win_chunks * c, slots=3)
+    restore_check(ctx, img, table)
+    new = [(i, t.clone()) for i, t in table]
+    workloads.mutate_runs(new, seed=c + 8, chunk=c, frac=0.3, run_mean=2)
+    codec_parity(ctx, new, c, prev_gpu=img, prev_oracle=oimg, window_bytes=win_chunks * c)
 
 
 def test_served_loop_rejects_codec_images_and_takes_plain_ones(ctx):
