@@ -6,10 +6,8 @@
 namespace mk {
 
 // classify: digest and kind of every chunk, nothing else (first pass of a
-// two-pass dump); gather: DATA chunks to their payload records at off[g]
-// (its last pass, after the offsets scan).
-enum Mode : int { kModeDump = 0, kModeDigest = 1, kModeVerify = 2, kModeRestore = 3, kModeClassify = 4,
-                  kModeGather = 5 };
+// two-pass dump; its last pass, the gather, is k_gather in gather.hip).
+enum Mode : int { kModeDump = 0, kModeDigest = 1, kModeVerify = 2, kModeRestore = 3, kModeClassify = 4 };
 
 // One launch of the chunk engine over global chunks [g0, g1).
 struct ChunkJob {
@@ -21,12 +19,12 @@ struct ChunkJob {
     const EngineConsts* ec;      // tables for (T, C)
     uint32_t* crc_out;           // dump / digest / classify: digest of chunk g at [g]
     uint8_t* kind_out;           // dump / classify: kind of chunk g at [g]
-    const uint8_t* kind_in;      // verify / restore / gather: kind of chunk g
+    const uint8_t* kind_in;      // verify / restore: kind of chunk g
     const uint32_t* ref_crc;     // verify / restore: expected digest of chunk g
     const uint32_t* prev_crc;    // dump / classify: previous digest table or nullptr
-    uint8_t* slot;               // staging window (dump, gather: written; restore: read)
-    const uint64_t* off;         // restore / gather: payload offset of chunk g
-    uint64_t slot_base;          // restore / gather: payload offset of the window start
+    uint8_t* slot;               // staging window (dump: written; restore: read)
+    const uint64_t* off;         // restore: payload offset of chunk g
+    uint64_t slot_base;          // restore: payload offset of the window start
     uint64_t* status;            // dump: look-back status, indexed by g - g0
     uint64_t* wtotal;            // dump: payload bytes of the window
     unsigned long long* bad;     // verify / restore: lowest failing chunk (init ~0)

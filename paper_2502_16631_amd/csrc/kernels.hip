@@ -332,7 +332,7 @@ k_chunks(JobList jl) {
     // The dump mode's look-back needs chunks taken in ticket order, and the
     // restore mode keeps it (concurrently processed chunks stay adjacent in
     // HBM: 5.2-5.8 TB/s against 4.7 TB/s grid-stride on the training state);
-    // the verify, gather, digest and classify modes take chunks grid-stride,
+    // the verify, digest and classify modes take chunks grid-stride,
     // so a chunk they skip costs no atomic and no barrier (a barrier follows
     // each chunk they process, for the LDS reductions).
     constexpr bool kTickets = MODE == kModeDump || MODE == kModeRestore;
@@ -363,12 +363,11 @@ k_chunks(JobList jl) {
         asm volatile("" : "+v"(lc), "+v"(ltid));
 
         uint8_t kd_in = kData;
-        if constexpr (MODE == kModeVerify || MODE == kModeRestore || MODE == kModeGather) {
+        if constexpr (MODE == kModeVerify || MODE == kModeRestore) {
             kd_in = job.kind_in[g];
             if (MODE == kModeVerify && kd_in != kUnchanged) continue;
             // UNCHANGED: nothing to write; PACKED: the codec's decode kernel
             if (MODE == kModeRestore && (kd_in == kUnchanged || kd_in == kPacked)) continue;
-            if (MODE == kModeGather && kd_in != kData) continue;
         }
         dirty = true;
         const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);
@@ -380,20 +379,7 @@ k_chunks(JobList jl) {
         const uint32_t init = full ? full_init : ad.tail_init;
         uint8_t* const aptr = reinterpret_cast<uint8_t*>(ad.ptr) + (k << log2c);
 
-        if constexpr (MODE == kModeGather) {
-            // a DATA chunk to its payload record (whole 16-byte blocks, the
-            // padding past len zero)
-            const uint64_t len16 = (len + 15u) & ~15u;
-            uint8_t* dst = job.slot + (job.off[g] - job.slot_base);
-            for (uint32_t p = 0; p < P; ++p) {
-                const uint64_t lp = (uint64_t)p * TILE;
-                if (lp >= len16) break;
-                v4u v[K];
-                load_rows<T, K>(v, aptr + lp, len - lp, ltid, active);
-                store_rows_padded<T, K>(v, dst + lp, len16 - lp, ltid, active);
-            }
-            continue;
-        } else if constexpr (MODE == kModeRestore) {
+        if constexpr (MODE == kModeRestore) {
             if (kd_in == kZero) {
                 const v4u z = vzero();
                 v4u zv[K];
@@ -900,7 +886,6 @@ hipError_t launch_tk(int mode, const JobList& jl, int grid, hipStream_t s) {
         case kModeDigest: hipLaunchKernelGGL((k_chunks<T, K, kModeDigest>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeVerify: hipLaunchKernelGGL((k_chunks<T, K, kModeVerify>), dim3(grid), dim3(NT), 0, s, jl); break;
         case kModeRestore: hipLaunchKernelGGL((k_chunks<T, K, kModeRestore>), dim3(grid), dim3(NT), 0, s, jl); break;
-        case kModeGather: hipLaunchKernelGGL((k_chunks<T, K, kModeGather>), dim3(grid), dim3(NT), 0, s, jl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -933,7 +918,6 @@ hipError_t occ_tk(int mode, int* n) {
         case kModeDigest: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeDigest>, NT, 0);
         case kModeVerify: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeVerify>, NT, 0);
         case kModeRestore: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeRestore>, NT, 0);
-        case kModeGather: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_chunks<T, K, kModeGather>, NT, 0);
         default: return hipErrorInvalidValue;
     }
 }
