@@ -146,6 +146,34 @@ def test_windows_slots_streams_and_shapes_do_not_change_the_image(ctx):
         restore_and_compare(ctx, img, table, **kw)
 
 
+def test_large_one_window_dump_and_corrupt_restore(ctx):
+    """A ~577 MB table held by one staging window (thousands of work-groups'
+    worth of chunks, allocations that end mid-chunk, zero regions, an empty
+    allocation): the image is the oracle's at two chunk sizes and restores;
+    a flipped byte near the end of the payload gives the oracle's code and
+    first bad chunk."""
+    gen = torch.Generator(device=DEV).manual_seed(61)
+    a = torch.randint(0, 256, ((300 << 20) + 4097,), dtype=torch.uint8, device=DEV, generator=gen)
+    a[(5 << 20):(25 << 20)] = 0
+    b = torch.randint(0, 256, ((250 << 20) + 33,), dtype=torch.uint8, device=DEV, generator=gen)
+    b[:(64 << 20)] = 0
+    s = torch.randint(0, 256, (999,), dtype=torch.uint8, device=DEV, generator=gen)
+    table = [(1, a), (2, torch.zeros(0, dtype=torch.uint8, device=DEV)), (3, b), (4, s)]
+    for c in (65536, 16384):
+        img, oimg, res = check_parity(ctx, table, c)
+        assert res.windows == 1
+        restore_and_compare(ctx, img, table)
+        img.free()
+    bad = oimg.copy()
+    bad[bad.size - 5000] ^= 0x10
+    want = corc.restore(bad, [(i, np.zeros(t.numel(), np.uint8)) for i, t in table])
+    rc, bimg = mk.ckpt_image_import(bad)
+    assert rc == 0
+    rc, rres = mk.ckpt_restore(ctx, bimg, [(i, torch.zeros_like(t)) for i, t in table])
+    assert (rc, rres.first_bad_chunk) == want and rc == mk.CKPT_ECORRUPT
+    bimg.free()
+
+
 def test_graph_replays_and_per_allocation_launches(ctx):
     """Batched form: the captured graph is replayed on new contents of the same
     table; the per-allocation launch baseline gives the same image."""
