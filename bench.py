@@ -96,6 +96,26 @@ def measured_traffic(workload, chunk, n_chunks):
     return rec.get("traffic_bytes_per_launch")
 
 
+def copy_kernel_rate(torch, nbytes=4 << 30, reps=5):
+    """Read + write GB/s of a plain elementwise pass (torch.bitwise_not over
+    nbytes into another buffer), median of reps: the measured copy-kernel
+    ceiling the dump kernel is compared with."""
+    src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.bitwise_not(src, out=dst)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.bitwise_not(src, out=dst)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.synchronize()
+    return 2.0 * nbytes / sorted(ts)[len(ts) // 2] / 1e9
+
+
 def build_workload(name, torch):
     import workloads
     if name == "training":
@@ -153,7 +173,7 @@ def cpu_baseline(table, chunk, budget_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="training", choices=["training", "tiny", "hpc", "fragmented"])
     ap.add_argument("--chunk", type=int, default=0)
@@ -202,6 +222,7 @@ def main():
     torch.bitwise_not(src, out=dst)
     torch.cuda.synchronize()
     del src, dst
+    copy_gbs = copy_kernel_rate(torch)
     table, chunk, wdesc = build_workload(args.workload, torch)
     if args.chunk:
         chunk = args.chunk
@@ -283,6 +304,7 @@ def main():
                      "traffic": measured_traffic(wdesc, chunk, nc),
                      "kernel": "dump-mode chunk kernel", "launches_per_dump": info["windows"],
                      "avg_launch_ms": round(k_avg / max(1, info["windows"]) * 1e3, 4),
+                     "copy_kernel_GBps": round(copy_gbs, 1), "frac_of_copy_kernel": round(achieved / copy_gbs, 4),
                      "restore_kernel_GBps": round((D + N) / (sum(rest_kern_ns) / len(rest_kern_ns) / 1e9) / 1e9, 1)},
     }
     if args.cpu_sample > 0:
