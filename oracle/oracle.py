@@ -17,7 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ckpt_oracle.c")
-LIB = os.path.join(HERE, "libckpt_oracle.so")
+# CKPT_ORACLE_LIB names another build of the same source (the tests load an
+# AddressSanitizer / UndefinedBehaviorSanitizer build this way)
+LIB = os.environ.get("CKPT_ORACLE_LIB") or os.path.join(HERE, "libckpt_oracle.so")
 NO_CHUNK = (1 << 64) - 1
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
