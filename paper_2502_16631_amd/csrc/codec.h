@@ -36,6 +36,10 @@ constexpr uint32_t kCodecMaxChunk = 65536;   // records are staged in LDS
 constexpr int kCodecThreads = 256;
 constexpr uint64_t kCodecPieces = 8;         // a codec dump's encode / copy-out pipeline depth
 constexpr uint32_t kRecordHead = 48;
+// What the size pass keeps of a PACKED chunk for its encode: the record head
+// (48 bytes), the 8 planes' 16-byte dictionaries and their used entries
+// (8 bytes), padded to 192 bytes.
+constexpr uint32_t kPackMeta = 192;
 enum : uint32_t { kPlaneRaw = 0, kPlaneConst = 1, kPlaneDict = 2 };
 
 inline bool codec_chunk_supported(uint32_t C) { return C >= kCodecMinChunk && C <= kCodecMaxChunk; }
@@ -55,6 +59,8 @@ struct PackJob {
     uint8_t* slot;           // encode: staging holding the payload from offset slot_base
     uint64_t slot_base;
     uint32_t* err;           // encode: set when a record's length differs from the size pass
+    uint8_t* meta;           // kPackMeta bytes per chunk (global index): size: written for PACKED
+                             // chunks; encode: read, in place of a second histogram
 };
 
 // encode = false: size pass; true: encode pass (PACKED chunks to slot + off[g]).

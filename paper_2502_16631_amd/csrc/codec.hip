@@ -125,9 +125,10 @@ constexpr int kHistStride = 8 * 256 + 1;
 
 template <int K, bool ENCODE>
 __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
-    __shared__ uint32_t s_hist[kHistCopies * kHistStride];
+    __shared__ uint32_t s_hist[ENCODE ? 1 : kHistCopies * kHistStride];
     __shared__ uint8_t s_code[8 * 256];
     __shared__ __align__(16) uint8_t s_dict[8 * 16];
+    __shared__ __align__(16) uint8_t s_meta[ENCODE ? kPackMeta : 16];
     __shared__ uint32_t s_mode[8], s_esc[8], s_nused[8];
     __shared__ unsigned long long s_w[2 * NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -153,60 +154,74 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
         // (coalesced); the encode pass needs each lane's rows consecutive
 #pragma unroll
         for (int r = 0; r < K; ++r) v[r] = ENCODE ? src[tid * K + r] : src[r * NT + tid];
-        for (int i = tid; i < kHistCopies * kHistStride; i += NT) s_hist[i] = 0;
-        if (ENCODE)
+        if constexpr (ENCODE) {
+            // modes, escape counts and dictionaries as the size pass chose them
             for (int i = tid; i < 8 * 256; i += NT) s_code[i] = 15;
-        __syncthreads();
-        uint32_t* hist = s_hist + (tid % kHistCopies) * kHistStride;
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-#pragma unroll
-            for (int b = 0; b < 16; ++b) atomicAdd(&hist[(b & 7) * 256 + byte_of(v[r], b)], 1u);
-        __syncthreads();
-        // dictionaries: wave w selects for planes w and w + 4, one value per
-        // round (largest count, then smallest value: key = count << 8 | 255 - v)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int p = wave + 4 * h;
-            uint32_t key[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t val = (uint32_t)lane + 64u * q;
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int cp = 0; cp < kHistCopies; ++cp) cnt += s_hist[cp * kHistStride + p * 256 + val];
-                key[q] = (cnt << 8) | (255u - val);
+            if (tid < (int)(kPackMeta / 16))
+                reinterpret_cast<uint4*>(s_meta)[tid] = reinterpret_cast<const uint4*>(j.meta + g * kPackMeta)[tid];
+            __syncthreads();
+            if (tid < 8) {
+                s_mode[tid] = s_meta[tid];
+                s_esc[tid] = (uint32_t)s_meta[8 + 4 * tid] | ((uint32_t)s_meta[9 + 4 * tid] << 8) |
+                             ((uint32_t)s_meta[10 + 4 * tid] << 16) | ((uint32_t)s_meta[11 + 4 * tid] << 24);
+                s_nused[tid] = s_meta[176 + tid];
             }
-            uint32_t covered = 0, n = 0, first = 0;
-            for (int i = 0; i < 15; ++i) {
-                const uint32_t m = wave_max(max(max(key[0], key[1]), max(key[2], key[3])));
-                if ((m >> 8) == 0) break;
-                const uint32_t val = 255u - (m & 255u), cnt = m >> 8;
-                if (i == 0) first = cnt;
-                covered += cnt;
-                ++n;
-                if (lane == 0) s_dict[p * 16 + i] = (uint8_t)val;
-                if (lane == (int)(val & 63u)) {
+            if (tid < 8 * 16) s_dict[tid] = s_meta[48 + tid];
+            __syncthreads();
+        } else {
+            for (int i = tid; i < kHistCopies * kHistStride; i += NT) s_hist[i] = 0;
+            __syncthreads();
+            uint32_t* hist = s_hist + (tid % kHistCopies) * kHistStride;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (q == (int)(val >> 6)) key[q] = 0;
+            for (int r = 0; r < K; ++r)
+#pragma unroll
+                for (int b = 0; b < 16; ++b) atomicAdd(&hist[(b & 7) * 256 + byte_of(v[r], b)], 1u);
+            __syncthreads();
+            // dictionaries: wave w selects for planes w and w + 4, one value per
+            // round (largest count, then smallest value: key = count << 8 | 255 - v)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = wave + 4 * h;
+                uint32_t key[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t val = (uint32_t)lane + 64u * q;
+                    uint32_t cnt = 0;
+#pragma unroll
+                    for (int cp = 0; cp < kHistCopies; ++cp) cnt += s_hist[cp * kHistStride + p * 256 + val];
+                    key[q] = (cnt << 8) | (255u - val);
+                }
+                uint32_t covered = 0, n = 0, first = 0;
+                for (int i = 0; i < 15; ++i) {
+                    const uint32_t m = wave_max(max(max(key[0], key[1]), max(key[2], key[3])));
+                    if ((m >> 8) == 0) break;
+                    const uint32_t val = 255u - (m & 255u), cnt = m >> 8;
+                    if (i == 0) first = cnt;
+                    covered += cnt;
+                    ++n;
+                    if (lane == 0) s_dict[p * 16 + i] = (uint8_t)val;
+                    if (lane == (int)(val & 63u)) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (q == (int)(val >> 6)) key[q] = 0;
+                    }
+                }
+                if (lane == 0) {
+                    for (uint32_t i = n; i < 16; ++i) s_dict[p * 16 + i] = 0;
+                    uint32_t mode = kPlaneRaw, esc = 0;
+                    if (n == 1 && first == L) {
+                        mode = kPlaneConst;
+                    } else if (section_len(L, kPlaneDict, L - covered) < section_len(L, kPlaneRaw, 0)) {
+                        mode = kPlaneDict;
+                        esc = L - covered;
+                    }
+                    s_mode[p] = mode;
+                    s_esc[p] = esc;
+                    s_nused[p] = n;
                 }
             }
-            if (lane == 0) {
-                for (uint32_t i = n; i < 16; ++i) s_dict[p * 16 + i] = 0;
-                uint32_t mode = kPlaneRaw, esc = 0;
-                if (n == 1 && first == L) {
-                    mode = kPlaneConst;
-                } else if (section_len(L, kPlaneDict, L - covered) < section_len(L, kPlaneRaw, 0)) {
-                    mode = kPlaneDict;
-                    esc = L - covered;
-                }
-                s_mode[p] = mode;
-                s_esc[p] = esc;
-                s_nused[p] = n;
-            }
+            __syncthreads();
         }
-        __syncthreads();
         uint32_t mode[8], esc[8], base[8];
         uint32_t rl = kRecordHead;
 #pragma unroll
@@ -224,6 +239,34 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
                 } else {
                     j.rlen[g] = C;
                 }
+            }
+            if (rl < C && tid < (int)(kPackMeta / 16)) {
+                // for the encode: head, dictionaries, used entries
+                uint32_t w[4] = {0, 0, 0, 0};
+                if (tid == 0) {
+                    w[0] = mode[0] | (mode[1] << 8) | (mode[2] << 16) | (mode[3] << 24);
+                    w[1] = mode[4] | (mode[5] << 8) | (mode[6] << 16) | (mode[7] << 24);
+                    w[2] = esc[0];
+                    w[3] = esc[1];
+                } else if (tid == 1) {
+                    w[0] = esc[2];
+                    w[1] = esc[3];
+                    w[2] = esc[4];
+                    w[3] = esc[5];
+                } else if (tid == 2) {
+                    w[0] = esc[6];
+                    w[1] = esc[7];
+                } else if (tid < 11) {
+                    const uint4 d = *reinterpret_cast<const uint4*>(&s_dict[(tid - 3) * 16]);
+                    w[0] = d.x;
+                    w[1] = d.y;
+                    w[2] = d.z;
+                    w[3] = d.w;
+                } else {
+                    w[0] = s_nused[0] | (s_nused[1] << 8) | (s_nused[2] << 16) | (s_nused[3] << 24);
+                    w[1] = s_nused[4] | (s_nused[5] << 8) | (s_nused[6] << 16) | (s_nused[7] << 24);
+                }
+                reinterpret_cast<uint4*>(j.meta + g * kPackMeta)[tid] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         } else {
             if (tid < 8 * 16) {

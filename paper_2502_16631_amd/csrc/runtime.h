@@ -131,7 +131,7 @@ struct ckpt_ctx {
     uint32_t epoch = 0;
     uint64_t use_clock = 0;
     // device buffers
-    mk::DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig, amap, rlen;
+    mk::DevBuf descs, status, ctl, arc, kinds, prevcrc, off, wb, staging, dig, amap, rlen, cmeta;
     std::map<std::pair<int, uint32_t>, mk::DevBuf> consts;    // (T, C) -> EngineConsts
     std::map<uint32_t, mk::DevBuf> cconsts;                   // C -> CodecConsts
     std::map<std::tuple<int, int, int>, int> occ;          // (T, K, mode) -> blocks per CU

@@ -501,7 +501,7 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (hipEvent_t e : c->tevents) hipEventDestroy(e);
     DevBuf* bufs[] = {&c->descs, &c->status, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
-                      &c->staging, &c->dig, &c->amap, &c->rlen};
+                      &c->staging, &c->dig, &c->amap, &c->rlen, &c->cmeta};
     for (DevBuf* b : bufs) b->release();
     for (auto& kv : c->consts) kv.second.release();
     for (auto& kv : c->cconsts) kv.second.release();
@@ -937,6 +937,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             return e;
         if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
         if ((e = c->rlen.ensure(4 * nc)) != hipSuccess) return e;
+        if ((e = c->cmeta.ensure((uint64_t)kPackMeta * nc)) != hipSuccess) return e;
         if ((e = ensure_hpin(c, 12 * nc)) != hipSuccess) return e;
         if (!c->s_aux && (e = hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
         if (!c->s_meta && (e = hipStreamCreateWithFlags(&c->s_meta, hipStreamNonBlocking)) != hipSuccess) return e;
@@ -970,6 +971,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         pj.off = c->off.as<uint64_t>();
         pj.slot = c->staging.as<uint8_t>();
         pj.err = err;
+        pj.meta = c->cmeta.as<uint8_t>();
         const bool one = W == 1;
         const uint64_t P = codec_p;
         std::vector<uint64_t> gb(P + 1);
