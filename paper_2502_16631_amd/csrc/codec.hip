@@ -418,17 +418,19 @@ __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen,
             if (tid == 0) atomicMin(job.bad, (unsigned long long)g);
             continue;
         }
-        // codes of the lane's rows and their escape counts
-        uint32_t cw[8][(K + 3) / 4];
+        // escape counts of the lane's codes (the codes are read again, plane
+        // by plane, when decoded: keeping all 8 planes' codes live across the
+        // scan costs a wave per SIMD)
         uint64_t ca = 0, cb = 0;
 #pragma unroll
         for (int p = 0; p < 8; ++p)
             if (mode[p] == kPlaneDict) {
-                load_bytes<K>(rec + base[p] + 16 + row0, cw[p]);
+                uint32_t cw[(K + 3) / 4];
+                load_bytes<K>(rec + base[p] + 16 + row0, cw);
                 uint32_t n15 = 0;
 #pragma unroll
                 for (int r = 0; r < K; ++r) {
-                    const uint32_t byte = byte_in(cw[p], r);
+                    const uint32_t byte = byte_in(cw, r);
                     n15 += ((byte & 15u) == 15u) + ((byte >> 4) == 15u);
                 }
                 if (p < 4) ca += (uint64_t)n15 << (16 * p);
@@ -445,54 +447,66 @@ __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen,
             continue;
         }
         const uint32_t esc_at = 16 + r16(L / 2);
-        uint32_t out[K][4];
+        // the lane's rows in parts of KH (at most 8 rows live at once; the
+        // escape positions of each plane carry over from part to part)
+        constexpr int KH = K < 8 ? K : 8;
+        uint32_t pre[8];
 #pragma unroll
-        for (int r = 0; r < K; ++r) out[r][0] = out[r][1] = out[r][2] = out[r][3] = 0;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int wl = p >> 2, sh = 8 * (p & 3);
-            if (mode[p] == kPlaneRaw) {
-                uint32_t w[(2 * K + 3) / 4];
-                load_bytes<2 * K>(rec + base[p] + 2 * row0, w);
-#pragma unroll
-                for (int r = 0; r < K; ++r) {
-                    out[r][wl] |= byte_in(w, 2 * r) << sh;
-                    out[r][2 + wl] |= byte_in(w, 2 * r + 1) << sh;
-                }
-            } else if (mode[p] == kPlaneConst) {
-                const uint32_t b = rec[base[p]];
-#pragma unroll
-                for (int r = 0; r < K; ++r) {
-                    out[r][wl] |= b << sh;
-                    out[r][2 + wl] |= b << sh;
-                }
-            } else {
-                uint32_t d[4];
-                load_bytes<16>(rec + base[p], d);
-                uint32_t pre = field16(ca, cb, p);
-                const uint8_t* escs = rec + base[p] + esc_at;
-#pragma unroll
-                for (int r = 0; r < K; ++r) {
-                    const uint32_t byte = byte_in(cw[p], r);
-                    const uint32_t c0 = byte & 15u, c1 = byte >> 4;
-                    const uint32_t b0 = c0 < 15 ? byte_in(d, c0) : escs[pre++];
-                    const uint32_t b1 = c1 < 15 ? byte_in(d, c1) : escs[pre++];
-                    out[r][wl] |= b0 << sh;
-                    out[r][2 + wl] |= b1 << sh;
-                }
-            }
-            asm volatile("" ::: "memory");   // one plane at a time (register pressure)
-        }
-        uint4* dst = reinterpret_cast<uint4*>(ad.ptr + k * C) + row0;
+        for (int p = 0; p < 8; ++p) pre[p] = field16(ca, cb, p);
         uint32_t crc = 0;
+#pragma unroll 1
+        for (int part = 0; part < K / KH; ++part) {
+            const uint32_t r0 = row0 + (uint32_t)part * KH;
+            uint32_t out[KH][4];
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            dst[r] = make_uint4(out[r][0], out[r][1], out[r][2], out[r][3]);
-            const uint32_t x[4] = {out[r][0] ^ crc, out[r][1], out[r][2], out[r][3]};
-            uint32_t c = 0;
+            for (int r = 0; r < KH; ++r) out[r][0] = out[r][1] = out[r][2] = out[r][3] = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) c ^= s_tab[i * 256 + byte_in(x, i)];
-            crc = c;
+            for (int p = 0; p < 8; ++p) {
+                const int wl = p >> 2, sh = 8 * (p & 3);
+                if (mode[p] == kPlaneRaw) {
+                    uint32_t w[(2 * KH + 3) / 4];
+                    load_bytes<2 * KH>(rec + base[p] + 2 * r0, w);
+#pragma unroll
+                    for (int r = 0; r < KH; ++r) {
+                        out[r][wl] |= byte_in(w, 2 * r) << sh;
+                        out[r][2 + wl] |= byte_in(w, 2 * r + 1) << sh;
+                    }
+                } else if (mode[p] == kPlaneConst) {
+                    const uint32_t b = rec[base[p]];
+#pragma unroll
+                    for (int r = 0; r < KH; ++r) {
+                        out[r][wl] |= b << sh;
+                        out[r][2 + wl] |= b << sh;
+                    }
+                } else {
+                    uint32_t d[4], cw[(KH + 3) / 4];
+                    load_bytes<16>(rec + base[p], d);
+                    load_bytes<KH>(rec + base[p] + 16 + r0, cw);
+                    const uint8_t* escs = rec + base[p] + esc_at;
+                    uint32_t q = pre[p];
+#pragma unroll
+                    for (int r = 0; r < KH; ++r) {
+                        const uint32_t byte = byte_in(cw, r);
+                        const uint32_t c0 = byte & 15u, c1 = byte >> 4;
+                        const uint32_t b0 = c0 < 15 ? byte_in(d, c0) : escs[q++];
+                        const uint32_t b1 = c1 < 15 ? byte_in(d, c1) : escs[q++];
+                        out[r][wl] |= b0 << sh;
+                        out[r][2 + wl] |= b1 << sh;
+                    }
+                    pre[p] = q;
+                }
+                asm volatile("" ::: "memory");   // one plane at a time (register pressure)
+            }
+            uint4* dst = reinterpret_cast<uint4*>(ad.ptr + k * C) + r0;
+#pragma unroll
+            for (int r = 0; r < KH; ++r) {
+                dst[r] = make_uint4(out[r][0], out[r][1], out[r][2], out[r][3]);
+                const uint32_t x[4] = {out[r][0] ^ crc, out[r][1], out[r][2], out[r][3]};
+                uint32_t c = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) c ^= s_tab[i * 256 + byte_in(x, i)];
+                crc = c;
+            }
         }
         // r(chunk) = xor over lanes of r(segment t) * x^(8 * bytes after it)
         uint32_t xr = gf_mul(crc, lanec);
