@@ -1346,14 +1346,16 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     int nslots;
     pick_staging(c, o, nc, C, &slot, &nslots);
     if ((codec || gate) && !(o && o->window_bytes) && nc >= 2 * kCodecPieces) {
-        // codec images and images still being loaded: kCodecPieces windows,
-        // so that each window's decode (or the load of its payload) overlaps
-        // the next window's upload; a slot per window when the budget holds
-        // them (no window waits for a slot), else a ring of two or three.
-        // Plain images keep one window when they fit: pipelining them saved
-        // 9 ms of a 485 ms restore but left the next dump's kernel 4 %
-        // slower in a dump / restore loop
-        const uint64_t s2 = ceil_div(nc, kCodecPieces) * C;
+        // codec images and images still being loaded: kCodecPieces windows
+        // (kCodecPieces - 1 over all but the last 1/32 of the chunks, then a
+        // short one, so little decode is left once the upload ends), so that
+        // each window's decode (or the load of its payload) overlaps the next
+        // window's upload; a slot per window when the budget holds them (no
+        // window waits for a slot), else a ring of two or three. Plain images
+        // keep one window when they fit: pipelining them saved 9 ms of a
+        // 485 ms restore but left the next dump's kernel 4 % slower in a
+        // dump / restore loop
+        const uint64_t s2 = ceil_div(nc - nc / 32, kCodecPieces - 1) * C;
         const uint64_t fit = c->budget / s2;
         const int k = fit >= kCodecPieces ? (int)kCodecPieces : fit >= 3 ? 3 : fit >= 2 ? 2 : 0;
         if (k) {
