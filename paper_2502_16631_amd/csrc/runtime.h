@@ -153,6 +153,10 @@ struct ckpt_ctx {
 
 namespace mk {
 
+// Plain restores of at least this many bytes held by one staging window are
+// launched as all chunks but the last 1/64, then those.
+constexpr uint64_t kTailMinBytes = 512ull << 20;
+
 // Storage hooks. A dump told of a sink reports every payload copy into the
 // image as it is queued (segments of at most kSinkSegment bytes), so the
 // image can go to a file while the rest is still being copied; a restore

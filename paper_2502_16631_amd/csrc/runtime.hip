@@ -1352,8 +1352,9 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         // each window's decode (or the load of its payload) overlaps the next
         // window's upload; a slot per window when the budget holds them (no
         // window waits for a slot), else a ring of two or three. Plain images
-        // keep one window when they fit: pipelining them saved 9 ms of a
-        // 485 ms restore but left the next dump's kernel 4 % slower in a
+        // keep one window when they fit (launched in two parts below): eight
+        // windows saved 9 ms of a 485 ms restore but left the device idle
+        // between short launches, and the next dump's kernel 4 % slower in a
         // dump / restore loop
         const uint64_t s2 = ceil_div(nc - nc / 32, kCodecPieces - 1) * C;
         const uint64_t fit = c->budget / s2;
@@ -1373,6 +1374,15 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     } else {
         wins = plan_windows(d, nc, C, slot, per_alloc);
     }
+    // A plain restore of at least kTailMinBytes held by one window runs as a
+    // launch over all chunks but the last 1/64 and a launch over those, both
+    // uploads on one copy stream: the long launch runs while the short tail
+    // is uploaded (the tail's upload ends before the long launch does, so the
+    // device never waits idle between the two).
+    const bool tail = !per_alloc && !codec && !gate && !(o && o->window_bytes) && wins.size() == 1 && nc >= 128 &&
+                      nc * C >= kTailMinBytes;
+    const uint64_t g_tail = tail ? nc - nc / 64 : 0;
+    if (tail) wins = {Window{0, g_tail}, Window{g_tail, nc}};
     const uint64_t W = wins.size();
     const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
 
@@ -1461,7 +1471,7 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         oj.off = c->off.as<uint64_t>();
         // fixed-size windows take their payload boundaries from the scan;
         // per-allocation windows compute them on the host below
-        oj.per_window = per_alloc ? nc + 1 : std::max<uint64_t>(1, slot / C);
+        oj.per_window = per_alloc ? nc + 1 : tail ? g_tail : std::max<uint64_t>(1, slot / C);
         oj.wb = c->wb.as<uint64_t>();
         oj.n_windows = per_alloc ? 1 : W;
         oj.status = c->status.as<uint64_t>();
@@ -1651,9 +1661,10 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     }
     for (uint64_t w = 0; w < W && !merged; ++w) {
         const int s = (int)(w % nslots);
-        hipStream_t cs = c->s_copy[w % ncs];
-        uint8_t* sp = c->staging.as<uint8_t>() + (uint64_t)s * slot;
-        if (slot_used[s]) HIPCHK(hipStreamWaitEvent(cs, ev[W + s], 0));
+        // a tail split keeps the payload where one window holds it
+        hipStream_t cs = c->s_copy[tail ? 0 : w % ncs];
+        uint8_t* sp = c->staging.as<uint8_t>() + (tail ? wbeg[w] : (uint64_t)s * slot);
+        if (slot_used[s] && !tail) HIPCHK(hipStreamWaitEvent(cs, ev[W + s], 0));
         slot_used[s] = true;
         const uint64_t len = wend[w] - wbeg[w];
         if (len > slot) return CKPT_ECORRUPT;
