@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="serve: aggregate requests per second")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; this build has no multi-GPU path (each GPU's allocations form an "
+        print("bench.py measures one GPU; the library has no multi-GPU path (each GPU's allocations form an "
               "independent image), so --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
