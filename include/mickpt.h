@@ -110,7 +110,8 @@ typedef struct {
 typedef struct {
     uint64_t first_bad_chunk;   /* UINT64_MAX if none                                       */
     int32_t  hip_error;         /* first failing hipError_t, 0 if none                      */
-    uint32_t windows;           /* staging windows used                                     */
+    uint32_t windows;           /* staging windows used (a plain restore of >= 512 MiB held  */
+                                /* by one window is launched as two parts and reports 2)    */
     uint64_t n_logical;         /* N: sum of allocation sizes                               */
     uint64_t n_payload;         /* D: payload bytes                                         */
     uint64_t n_chunks;
