@@ -116,6 +116,36 @@ def copy_kernel_rate(torch, nbytes=4 << 30, reps=5):
     return 2.0 * nbytes / sorted(ts)[len(ts) // 2] / 1e9
 
 
+def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
+    """Read + write GB/s of the hand-written 128-bit copy kernel
+    (csrc/copyprobe.hip, four blocks in flight per thread, grid-stride),
+    best over a sweep of grid sizes, work-group widths and plain /
+    non-temporal stores: the measured copy ceiling of this GPU."""
+    import ctypes
+    so = os.path.join(ROOT, "paper_2502_16631_amd", "libmkcopy.so")
+    L = ctypes.CDLL(so)
+    L.mkcopy_run.restype = ctypes.c_int
+    L.mkcopy_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    best = None
+    for blocks in (1024, 2048, 4096, 8192, 16384):
+        for threads in (256, 512, 1024):
+            for nt in (0, 1):
+                ms = ctypes.c_float(0)
+                rc = L.mkcopy_run(dst.data_ptr(), src.data_ptr(), nbytes, blocks, threads, nt, reps, ctypes.byref(ms))
+                if rc != 0:
+                    raise RuntimeError("copy kernel: hip error %d" % rc)
+                gbs = 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+                if best is None or gbs > best["GBps"]:
+                    best = {"GBps": round(gbs, 1), "blocks": blocks, "threads": threads, "nt_stores": bool(nt)}
+    del src, dst
+    torch.cuda.synchronize()
+    return best
+
+
 def build_workload(name, torch):
     import workloads
     if name == "training":
@@ -130,13 +160,30 @@ def build_workload(name, torch):
     raise SystemExit("unknown workload " + name)
 
 
-def cpu_baseline(table, chunk, budget_bytes):
+def host_cpu():
+    """CPU model and the number of host cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(table, chunk, budget_bytes, mk):
     """The CPU oracle (plain C, Sarwate CRC) on the first allocations of the
     workload up to budget_bytes; device bytes are copied to the host first
-    (not timed)."""
+    (not timed). The same sample is then dumped on the GPU and the two
+    images are compared: SHA-256 (over 256 MiB pieces) of the whole image,
+    the full crc[] and kind[] tables."""
     import numpy as np
     from oracle import oracle
     import workloads
+    from bench_forms import piece_sha256
     sample, total = [], 0
     for i, t in table:
         nb = t.numel() * t.element_size()
@@ -152,7 +199,6 @@ def cpu_baseline(table, chunk, budget_bytes):
     rc, img = oracle.dump(host, chunk, threads=threads)
     dt = time.perf_counter() - t0
     assert rc == 0
-    del img
     # one thread, on the first allocations up to 1 GB of the same sample
     one, n1 = [], 0
     for i, a in host:
@@ -164,10 +210,28 @@ def cpu_baseline(table, chunk, budget_bytes):
     rc, _ = oracle.dump(one, chunk, threads=1)
     d1 = time.perf_counter() - t1
     assert rc == 0
-    return {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "full dump of %d of the workload's allocations (%.2f GB), %d threads, %.1f s"
-                      % (len(sample), total / 1e9, threads, dt),
-            "single_thread_GBps": round(n1 / d1 / 1e9, 3)}
+    del host, one
+    # the GPU image of the same sample, compared with the oracle's
+    ctx = mk.ckpt_ctx_create(0, total + (1 << 30))
+    rc, gimg, _ = mk.ckpt_dump(ctx, sample, opts=mk.make_opts(chunk_size=chunk))
+    assert rc == 0, mk.ckpt_strerror(rc)
+    g = gimg.view()
+    n, nc = len(sample), int(np.frombuffer(img[24:32].tobytes(), np.uint64)[0])
+    o_crc, o_kind = 64 + 32 * n, 64 + 32 * n + 4 * nc
+    sha_o, sha_g = piece_sha256(img), piece_sha256(g)
+    parity = {"sha256_equal": sha_o == sha_g and g.size == img.size, "image_bytes": int(img.size),
+              "crc_equal": bool(np.array_equal(g[o_crc:o_kind], img[o_crc:o_kind])),
+              "kind_equal": bool(np.array_equal(g[o_kind:o_kind + nc], img[o_kind:o_kind + nc])),
+              "n_chunks": nc, "sha256": sha_o[:16]}
+    gimg.free()
+    mk.ckpt_ctx_destroy(ctx)
+    del img
+    out = {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": "full dump of %d of the workload's allocations (%.2f GB), %d threads, %.1f s"
+                     % (len(sample), total / 1e9, threads, dt),
+           "single_thread_GBps": round(n1 / d1 / 1e9, 3), "parity": parity}
+    out.update(host_cpu())
+    return out
 
 
 def main():
@@ -196,6 +260,9 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="scale the total bytes of the non-plain forms")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: aggregate requests per second")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="plain form: also run the incremental and batched forms (compact, 1 + 3 steps each) and "
+                         "report them under 'forms' (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (each GPU's allocations form an "
@@ -223,6 +290,7 @@ def main():
     torch.cuda.synchronize()
     del src, dst
     copy_gbs = copy_kernel_rate(torch)
+    copy_hw = copy_kernel_ceiling(torch)
     table, chunk, wdesc = build_workload(args.workload, torch)
     if args.chunk:
         chunk = args.chunk
@@ -304,11 +372,20 @@ def main():
                      "traffic": measured_traffic(wdesc, chunk, nc),
                      "kernel": "dump-mode chunk kernel", "launches_per_dump": info["windows"],
                      "avg_launch_ms": round(k_avg / max(1, info["windows"]) * 1e3, 4),
-                     "copy_kernel_GBps": round(copy_gbs, 1), "frac_of_copy_kernel": round(achieved / copy_gbs, 4),
+                     "copy_kernel_GBps": copy_hw["GBps"], "copy_kernel": copy_hw,
+                     "frac_of_copy_kernel": round(achieved / copy_hw["GBps"], 4),
+                     "torch_bitwise_not_GBps": round(copy_gbs, 1),
                      "restore_kernel_GBps": round((D + N) / (sum(rest_kern_ns) / len(rest_kern_ns) / 1e9) / 1e9, 1)},
     }
     if args.cpu_sample > 0:
-        line["cpu_baseline"] = cpu_baseline(table, chunk, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(table, chunk, args.cpu_sample, mk)
+    if args.forms and args.workload == "training":
+        # the incremental (HPC image) and batched (fragmented) forms, compact
+        import bench_forms
+        del table, ref
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        line["forms"] = bench_forms.summary(args, torch, mk, link)
     print(json.dumps(line), flush=True)
 
 

@@ -50,6 +50,8 @@ extern "C" {
                               state (first_bad_chunk set), or merge with the wrong base       */
 #define CKPT_ETIMEOUT  -7  /* serving: request deadline passed before completion            */
 #define CKPT_EIO       -8  /* a file could not be opened, written, synced or read            */
+#define CKPT_ELIMIT    -9  /* a dump into fixed buffers: the table, its previous image or the
+                              chunk size exceeds what the buffers hold (nothing done)         */
 
 /* chunk kinds stored in an image */
 #define CKPT_KIND_ZERO      0
@@ -103,7 +105,11 @@ typedef struct {
     uint32_t slots;          /* staging ring slots; 0 = chosen from the budget              */
     uint64_t window_bytes;   /* staging slot size; 0 = chosen from the budget               */
     uint32_t flags;          /* CKPT_OPT_*                                                  */
-    uint32_t reserved;       /* must be 0                                                   */
+    uint32_t strict_verify;  /* restore: 1 = after the writes, re-read every restored chunk
+                                from HBM and check its CRC-32C again (the default check runs
+                                on the data in registers as it is written; section 6 asks
+                                for deterministic restores); 0 = off; other values:
+                                CKPT_EINVAL. dump: ignored                                   */
 } ckpt_opts;
 
 /* Optional per-call report. */
@@ -122,14 +128,40 @@ typedef struct {
     uint64_t ns_link;           /* wall time from first to last host-link copy              */
     uint64_t n_packed;          /* PACKED chunks (codec records; not counted in n_data)     */
     uint64_t reserved[3];
+    /* Time per stage in ns (section 5.1 measures checkpoint and restore by the
+     * time spent in each of their stages). 0 when a stage did not run or, for
+     * device stages, with CKPT_OPT_NO_TIMING;
+     * device stages are HIP-event times on the stream they run on, link and host
+     * stages wall times).
+     * dump:    [0] set-up (descriptors, chunk map, table clears)  [1] chunk kernels
+     *          on the main stream (single pass: the whole dump kernel, which also
+     *          scans and gathers; delta in one window: digest + kind pass; codec:
+     *          digest + kind and size passes)  [2] offsets scan (delta in one
+     *          window)  [3] gather (delta in one window) or gather + encode
+     *          (codec)  [4] host link: first to last payload copy, wall time
+     *          [5] finalize (per-allocation combine, table digests, tables copied
+     *          out)  [6] unused  [7] whole call, wall time;
+     * restore: [0] validate (tables up, digest, offsets scan, host checks), wall
+     *          time  [1] base check of a delta, wall time  [2] host link: first to
+     *          last payload copy, wall time  [3] scatter + fused verify kernels
+     *          (codec decode included)  [4] strict re-read  [5] finalize
+     *          (per-allocation check)  [6] unused  [7] whole call, wall time. */
+    uint64_t ns_stage[8];
 } ckpt_result;
 
 /* ------------------------------------------------------------------ context */
-/* Create a context on HIP device `device`. staging_budget = bytes of device
- * memory the context may use for staging windows (0 = 4 GiB). Returns
- * CKPT_OK and *out, or an error and *out = NULL. */
+/* The paper defines no such call: a context is this library's holder of the
+ * device resources its calls share. Its nearest counterpart in the paper is
+ * the plugin's initialization callback (section 3.1), which runs once before
+ * the operations. Create a context on HIP device `device`. staging_budget =
+ * bytes of device memory the context may use for staging windows (0 = 4 GiB).
+ * Set-up made here once: the streams, events and pinned scratch the calls
+ * use.
+ * Returns CKPT_OK and *out, or an error (CKPT_EINVAL for a device that does
+ * not exist, CKPT_EHIP / CKPT_ENOMEM when the set-up fails) and *out = NULL. */
 int  ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** out);
-/* Free a context and everything it owns except images. NULL is a no-op. */
+/* Free a context and everything it owns except images (the counterpart of
+ * the plugin's exit callback, section 3.1). NULL is a no-op. */
 void ckpt_ctx_destroy(ckpt_ctx* ctx);
 
 /* ------------------------------------------------------------------ dump */
@@ -151,7 +183,9 @@ int  ckpt_dump(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* p
  * `table` matches it (count, ids, sizes in order: CKPT_EMISMATCH), then
  * writes DATA chunks from the payload and zero-fills ZERO chunks,
  * verifying every written chunk and every allocation against the image's
- * digests. A delta image is applied in place: its UNCHANGED chunks must
+ * digests (with opts->strict_verify also by re-reading every restored chunk
+ * once all writes are done; the lowest failing chunk of either check is
+ * reported). A delta image is applied in place: its UNCHANGED chunks must
  * already hold the base state, which is checked before anything is written
  * (CKPT_EBASE). After a CKPT_ECORRUPT the contents of the allocations are
  * unspecified. */
@@ -172,7 +206,7 @@ int  ckpt_restore_some(ckpt_ctx* ctx, const ckpt_image* img, const ckpt_alloc_ta
                        const ckpt_opts* opts, void* stream, ckpt_result* res);
 
 /* ------------------------------------------------------------------ autotuner */
-/* Batched form: choose chunk size (16, 64 or 256 KiB), work-group width and
+/* This library's own call: the paper tunes nothing. Batched form: choose chunk size (16, 64 or 256 KiB), work-group width and
  * copy-stream count for `table` by timing trial dumps of a bounded sample of
  * it (allocations spread over the table, about sample_bytes in total; 0 =
  * 2 GB). flags are the CKPT_OPT_* flags the caller will dump with. Fills
@@ -184,23 +218,30 @@ int  ckpt_autotune(ckpt_ctx* ctx, const ckpt_alloc_table* table, uint64_t sample
                    ckpt_opts* best, double* gbps);
 
 /* ------------------------------------------------------------------ host ops */
-/* Fold a delta into the full image of its base (host memory only): the
- * result equals a full dump of the delta's state. CKPT_EINVAL if base is a
+/* The image format's own calls (the paper defines no image format).
+ * ckpt_merge folds a delta into the full image of its base (host memory
+ * only): the result equals a full dump of the delta's state. Section 7
+ * names incremental / differential checkpointing among the optimisations the
+ * method can take on; merging is how a chain of such images is compacted. CKPT_EINVAL if base is a
  * delta or delta is not one, CKPT_EBASE if delta was not taken against
  * base. */
 int  ckpt_merge(const ckpt_image* base, const ckpt_image* delta, ckpt_image** out);
-/* Borrow the bytes of an image (valid until ckpt_image_free). */
+/* Borrow the bytes of an image (valid until ckpt_image_free): the image's
+ * memory stays the library's; *p and *n describe it. */
 int  ckpt_image_bytes(const ckpt_image* img, const void** p, uint64_t* n);
-/* Copy n bytes into a new image after validating header, tables digest and
- * structure (CKPT_ECORRUPT if invalid). */
+/* Copy n bytes (the caller's, only read) into a new image owned by the
+ * library after validating header, tables digest and structure
+ * (CKPT_ECORRUPT if invalid; payload records are verified by a restore). */
 int  ckpt_image_import(const void* p, uint64_t n, ckpt_image** out);
-/* Free an image. NULL is a no-op. */
+/* Free an image (its memory returns to the library's pinned pool). NULL is a
+ * no-op. */
 void ckpt_image_free(ckpt_image* img);
 
-/* Storage (section 3.2: the AMD GPU plugin saves the GPU state into
- * checkpoint files; section 5.1 measures the memory write time to persistent
- * storage, and section 5.2 finds restores bounded also by loading checkpoint
- * data from disk). ckpt_image_save writes the image's bytes to `path`
+/* Storage. In the paper's checkpoint/restore workflow (section 3.2, its
+ * second step) the AMD GPU plugin writes the captured GPU state, whose buffer
+ * objects section 3.1.2 lists, out to checkpoint files; section 5.1 times
+ * the write of the memory state to persistent storage, and section 5.2 finds
+ * restores bounded also by how fast checkpoint data is read from disk. ckpt_image_save writes the image's bytes to `path`
  * (created or truncated) with `threads` threads (0 = 8) of positional writes,
  * O_DIRECT for the page-aligned prefix when the file system accepts it, and
  * syncs the file before returning. ckpt_image_load reads such a file into a
@@ -211,10 +252,8 @@ void ckpt_image_free(ckpt_image* img);
 int  ckpt_image_save(const ckpt_image* img, const char* path, uint32_t threads);
 int  ckpt_image_load(const char* path, uint32_t threads, ckpt_image** out);
 /* Dump straight to a file, and restore straight from one, with the file I/O
- * overlapping the host-link copies (the paper's checkpoint images live on
- * storage, section 3.2; section 5.1 measures the write of the memory state
- * to persistent storage and section 5.2 finds restores bounded also by
- * loading checkpoint data from disk).
+ * overlapping the host-link copies (checkpoint files: section 3.2; their
+ * write and read times: sections 5.1 and 5.2).
  * ckpt_dump_file: as ckpt_dump, and the image is written to `path` (created
  * or truncated) by `io_threads` threads (0 = 8) as the dump copies it out:
  * every 64 MiB piece of the file goes to disk as soon as all its bytes are
@@ -235,13 +274,18 @@ int  ckpt_dump_file(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_ima
                     ckpt_image** out);
 int  ckpt_restore_file(ckpt_ctx* ctx, const char* path, uint32_t io_threads, const ckpt_alloc_table* table,
                        const ckpt_opts* opts, void* stream, ckpt_result* res);
-/* Static description of an error code. */
+/* Static description of an error code (this library's own call). */
 const char* ckpt_strerror(int code);
-/* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes. */
+/* CRC-32C (reflected 0x82F63B78, preset and final complement) of host bytes:
+ * the image format's chunk digest (this library's choice; the paper names
+ * none), exposed so that callers can check images. */
 uint32_t ckpt_crc32c(const void* p, uint64_t n);
 
 /* ------------------------------------------------------------------ serving */
-/* A request loop over one context (served form). Dump and restore requests
+/* The paper defines no serving loop; section 7 relates GPU inference on
+ * serverless platforms and on-demand restore of GPU workloads, where many
+ * tenants' checkpoints and restores share one device. This loop is the
+ * library's. A request loop over one context (served form). Dump and restore requests
  * from many tenants are admitted in arrival order as lanes and staging
  * memory free up (each admitted request holds two staging windows of the
  * budget); the next ready window of every admitted request joins one shared

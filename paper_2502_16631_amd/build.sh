@@ -30,3 +30,7 @@ hipcc --offload-arch=gfx950 -shared -fPIC -o "$OUT.tmp" "$BUILD/kernels.o" "$BUI
     "$BUILD/hostmath.o" "$BUILD/storage.o" -lpthread
 mv "$OUT.tmp" "$OUT"
 echo "built $OUT"
+# the benchmark's copy-kernel ceiling (measurement only, not the library)
+hipcc "${FLAGS[@]}" -shared -o "$HERE/libmkcopy.so.tmp" "$SRC/copyprobe.hip"
+mv "$HERE/libmkcopy.so.tmp" "$HERE/libmkcopy.so"
+echo "built $HERE/libmkcopy.so"

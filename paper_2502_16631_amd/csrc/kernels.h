@@ -30,8 +30,12 @@ struct ChunkJob {
     unsigned long long* bad;     // verify / restore: lowest failing chunk (init ~0)
     uint32_t* err;               // internal error flag (look-back time-out)
     uint32_t epoch;              // look-back epoch of this launch (1 .. 2^22-1)
-    uint32_t pad;
+    uint32_t flags;              // kJob*
+    const uint32_t* gate;        // restore / verify: when set and 0 at launch, the launch does nothing
 };
+// verify mode: check every chunk of the range whatever its kind (the strict
+// re-read after a restore), not only UNCHANGED ones
+constexpr uint32_t kJobVerifyAll = 1;
 
 // Several jobs in one persistent launch (continuous batching): the jobs'
 // chunk ranges are laid end to end in one ticket space; every job keeps its
@@ -65,6 +69,8 @@ struct OffJob {
     uint32_t* err;
     uint32_t epoch;
     uint32_t pad;
+    uint64_t g_base;             // the scan covers global chunks [g_base, g_base + n_chunks); off, kind
+                                 // and amap are indexed globally, windows and wb relative to g_base
 };
 
 // Per-allocation combine of chunk digests into the whole-allocation CRC.
@@ -82,7 +88,23 @@ struct CombineJob {
     int pad;
 };
 
+// Validation of a restore inside a captured graph: *gate = 1 when the
+// tables digest combined from the device's two halves equals the expected
+// value, the kinds are all ZERO or DATA and the payload total equals the
+// expected D; else 0 (the gated kernels then write nothing).
+struct GateJob {
+    const uint32_t* dig;                 // [2]: digest of AllocRec || crc[], of kind[] || pad
+    uint32_t xlen;                       // x^(8 len(kind[] || pad))
+    uint32_t pad;
+    const unsigned long long* counts;    // [4]: zero, data, unchanged, invalid
+    const uint64_t* total;               // payload total of the offsets scan
+    uint64_t n_chunks;
+    const uint64_t* expect;              // [2]: tables digest, D (written before each launch)
+    uint32_t* gate;
+};
+
 bool tile_supported(int T, int K);
+hipError_t launch_gate(const GateJob& job, hipStream_t s);
 hipError_t launch_chunks(int T, int K, int mode, const JobList& jl, int grid, hipStream_t s);
 hipError_t chunks_occupancy(int T, int K, int mode, int* blocks_per_cu);
 hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s);

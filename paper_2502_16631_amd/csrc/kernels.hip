@@ -24,7 +24,8 @@
 //             is read from HBM once);
 //   digest  - digest only (used for the image's table digests);
 //   verify  - digest of UNCHANGED chunks compared with the image (delta
-//             restore checks that the target holds the base);
+//             restore checks that the target holds the base), or of every
+//             chunk (kJobVerifyAll: the strict re-read after a restore);
 //   restore - DATA chunks read from the staging window, stored to their
 //             allocation and verified on the data in registers; ZERO chunks
 //             zero-filled (PACKED chunks are left to the codec's decode).
@@ -67,6 +68,17 @@ __device__ inline void lb_publish(uint64_t* status, uint64_t idx, uint64_t agg, 
     st_relaxed(&status[idx], (idx == 0 ? kStInc : kStAgg) | tag | agg);
 }
 
+// The walk reads kWalk status words per lane per step (64 kWalk
+// predecessors), issued together so that one memory latency covers them:
+// status words are read at device scope, which on a multi-die GPU is a
+// round trip past the dies' L2 caches, and the nearest inclusive prefix is
+// often hundreds of positions back.
+constexpr int kWalk = 4;
+
+__device__ inline bool lb_valid(uint64_t w, uint32_t epoch) {
+    return (w >> 62) != 0 && ((w >> 40) & kEpochMask) == (epoch & kEpochMask);
+}
+
 __device__ uint64_t lb_walk(uint64_t* status, uint64_t idx, uint64_t agg, uint32_t epoch, uint32_t* err) {
     const int lane = threadIdx.x & 63;
     const uint64_t tag = (uint64_t)(epoch & kEpochMask) << 40;
@@ -74,31 +86,55 @@ __device__ uint64_t lb_walk(uint64_t* status, uint64_t idx, uint64_t agg, uint32
     uint64_t excl = 0;
     int64_t base = (int64_t)idx - 1;
     for (;;) {
-        const int64_t j = base - lane;
-        uint64_t w = kStInc | tag;          // before the start: inclusive 0
-        if (j >= 0) {
-            uint32_t spins = 0;
-            for (;;) {
-                w = ld_relaxed(&status[j]);
-                if ((w >> 62) != 0 && ((w >> 40) & kEpochMask) == (epoch & kEpochMask)) break;
-                if (++spins > kMaxSpins) {   // bounded wait: report, never hang
-                    atomicOr(err, 1u);
-                    w = kStInc | tag;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+        // lane l holds positions base - (l kWalk + i), i = 0 .. kWalk-1 (i = 0 nearest)
+        uint64_t w[kWalk];
+#pragma unroll
+        for (int i = 0; i < kWalk; ++i) {
+            const int64_t j = base - (int64_t)(lane * kWalk + i);
+            w[i] = j >= 0 ? ld_relaxed(&status[j]) : (kStInc | tag);   // before the start: inclusive 0
         }
-        const bool inc = (w >> 62) == 2;
-        const uint64_t val = w & kStValueMask;
-        const uint64_t incmask = __ballot(inc);
+        uint32_t spins = 0;
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int i = 0; i < kWalk; ++i) {
+                if (!lb_valid(w[i], epoch)) {
+                    w[i] = ld_relaxed(&status[base - (int64_t)(lane * kWalk + i)]);
+                    all = all && lb_valid(w[i], epoch);
+                }
+            }
+            if (all) break;
+            if (++spins > kMaxSpins) {   // bounded wait: report, never hang
+                atomicOr(err, 1u);
+#pragma unroll
+                for (int i = 0; i < kWalk; ++i)
+                    if (!lb_valid(w[i], epoch)) w[i] = kStInc | tag;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        // the nearest inclusive prefix of this lane (kWalk if none)
+        int first = kWalk;
+#pragma unroll
+        for (int i = kWalk - 1; i >= 0; --i)
+            if ((w[i] >> 62) == 2) first = i;
+        const uint64_t incmask = __ballot(first < kWalk);
         if (incmask) {
-            const int first = __ffsll((unsigned long long)incmask) - 1;
-            excl += wave_sum_u64(lane <= first ? val : 0);
+            // lanes before the first lane holding one add all their values;
+            // that lane adds up to its inclusive prefix, later lanes nothing
+            const int fl = __ffsll((unsigned long long)incmask) - 1;
+            uint64_t v = 0;
+#pragma unroll
+            for (int i = 0; i < kWalk; ++i)
+                if (lane < fl || (lane == fl && i <= first)) v += w[i] & kStValueMask;
+            excl += wave_sum_u64(v);
             break;
         }
-        excl += wave_sum_u64(val);
-        base -= 64;
+        uint64_t v = 0;
+#pragma unroll
+        for (int i = 0; i < kWalk; ++i) v += w[i] & kStValueMask;
+        excl += wave_sum_u64(v);
+        base -= 64 * kWalk;
     }
     if (lane == 0) st_relaxed(&status[idx], kStInc | tag | (excl + agg));
     return excl;
@@ -315,6 +351,9 @@ k_chunks(JobList jl) {
 
     const int tid = threadIdx.x;
     const bool active = T >= 64 || tid < T;
+    // a restore that its graph's validation rejected writes nothing
+    if constexpr (MODE == kModeRestore || MODE == kModeVerify)
+        if (jl.job[0].gate && *jl.job[0].gate == 0) return;
     const EngineConsts* ec = jl.job[0].ec;
     for (int i = tid; i < 16 * 256; i += NT) s_dt[i] = ec->dt[i];
     const uint32_t lanec = active ? ec->lane[tid] : 0u;
@@ -365,7 +404,7 @@ k_chunks(JobList jl) {
         uint8_t kd_in = kData;
         if constexpr (MODE == kModeVerify || MODE == kModeRestore) {
             kd_in = job.kind_in[g];
-            if (MODE == kModeVerify && kd_in != kUnchanged) continue;
+            if (MODE == kModeVerify && kd_in != kUnchanged && !(job.flags & kJobVerifyAll)) continue;
             // UNCHANGED: nothing to write; PACKED: the codec's decode kernel
             if (MODE == kModeRestore && (kd_in == kUnchanged || kd_in == kPacked)) continue;
         }
@@ -738,12 +777,13 @@ __global__ void __launch_bounds__(256) k_offsets(OffJob job) {
         const uint64_t g = g0 + tid;
         uint64_t plen = 0;
         uint32_t cz = 0, cd = 0, cu = 0, ci = 0;
+        const uint64_t gg = job.g_base + g;   // global chunk
         if (g < job.n_chunks) {
-            const uint8_t kd = job.kind[g];
-            const uint32_t a = job.amap ? job.amap[g] : find_alloc(job.allocs, job.n_allocs, g);
+            const uint8_t kd = job.kind[gg];
+            const uint32_t a = job.amap ? job.amap[gg] : find_alloc(job.allocs, job.n_allocs, gg);
             const uint64_t first = job.allocs[a].first, size = job.allocs[a].size;
             const uint64_t nk = (size + job.C - 1) / job.C;
-            const uint64_t len = (g - first + 1 == nk) ? job.allocs[a].tail_len : job.C;
+            const uint64_t len = (gg - first + 1 == nk) ? job.allocs[a].tail_len : job.C;
             if (kd == kData) { plen = (len + 15) & ~15ull; cd = 1; }
             else if (kd == kZero) cz = 1;
             else if (kd == kUnchanged) cu = 1;
@@ -780,11 +820,19 @@ __global__ void __launch_bounds__(256) k_offsets(OffJob job) {
         __syncthreads();
         const uint64_t o = s_off + local;
         if (g < job.n_chunks) {
-            job.off[g] = o;
+            job.off[gg] = o;
             if (g % job.per_window == 0) job.wb[g / job.per_window] = o;
             if (g + 1 == job.n_chunks) job.wb[job.n_windows] = o + plen;
         }
     }
+}
+
+__global__ void k_gate(GateJob j) {
+    if (threadIdx.x != 0) return;
+    const uint32_t tcrc = gf_mul(j.dig[0], j.xlen) ^ j.dig[1];
+    const bool ok = tcrc == (uint32_t)j.expect[0] && j.counts[3] == 0 && j.counts[2] == 0 &&
+                    j.counts[0] + j.counts[1] == j.n_chunks && *j.total == j.expect[1];
+    *j.gate = ok ? 1u : 0u;
 }
 
 __device__ inline uint32_t xpow8(uint64_t n, const uint32_t* x2n) {   // x^(8n)
@@ -953,6 +1001,11 @@ hipError_t chunks_occupancy(int T, int K, int mode, int* n) {
 
 hipError_t launch_offsets(const OffJob& job, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_offsets, dim3(grid), dim3(256), 0, s, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate(const GateJob& job, hipStream_t s) {
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, s, job);
     return hipGetLastError();
 }
 

@@ -234,15 +234,6 @@ namespace mk {
         }                                                        \
     } while (0)
 
-uint32_t next_epoch(ckpt_ctx* c, bool* wrapped) {
-    *wrapped = false;
-    if (++c->epoch > kEpochMask) {
-        c->epoch = 1;
-        *wrapped = true;
-    }
-    return c->epoch;
-}
-
 // Tile shape for a chunk size: threads T and rows K per pass (16 T K <= C).
 void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K) {
     if (C <= 512) { *T = (int)(C / 16); *K = 1; return; }
@@ -357,6 +348,16 @@ uint64_t timed_ns(ckpt_ctx* c, size_t n) {
     return (uint64_t)(total * 1e6);
 }
 
+// Device time between two recorded timing events, in ns (0 if unavailable).
+uint64_t span_ns(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (uint64_t)((double)ms * 1e6);
+}
+
 hipError_t ensure_events(ckpt_ctx* c, size_t n) {
     while (c->events.size() < n) {
         hipEvent_t e;
@@ -426,13 +427,8 @@ void fill_result(ckpt_result* res) {
 
 // Make the context's main stream wait for prior work on the caller's stream.
 hipError_t order_after(ckpt_ctx* c, void* stream) {
-    if (ensure_events(c, 1) != hipSuccess) return hipErrorOutOfMemory;
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev, static_cast<hipStream_t>(stream));
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->s_main, ev, 0);
-    hipEventDestroy(ev);
+    hipError_t e = hipEventRecord(c->ev_order, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->s_main, c->ev_order, 0);
     return e;
 }
 
@@ -465,6 +461,16 @@ void pick_staging(const ckpt_ctx* c, const ckpt_opts* o, uint64_t n_chunks, uint
 }  // namespace
 
 // ------------------------------------------------------------ context API
+static hipError_t ensure_copy_streams(ckpt_ctx* c, uint32_t n) {
+    while (c->s_copy.size() < n) {
+        hipStream_t s;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        c->s_copy.push_back(s);
+    }
+    return hipSuccess;
+}
+
 extern "C" int ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** out) {
     if (!out) return CKPT_EINVAL;
     *out = nullptr;
@@ -477,30 +483,39 @@ extern "C" int ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** o
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return CKPT_EHIP; }
     c->num_cu = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&c->s_main, hipStreamNonBlocking) != hipSuccess) { delete c; return CKPT_EHIP; }
+    // Set-up: streams, events, pinned scratch and the device's static array
+    // are made here once, so that a no-allocation dump makes none of them.
+    hipError_t e = hipStreamCreateWithFlags(&c->s_main, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_order, hipEventDisableTiming);
+    if (e == hipSuccess) e = ensure_copy_streams(c, 2);
+    if (e == hipSuccess) e = ensure_events(c, 16);
+    if (e == hipSuccess) e = ensure_tevents(c, 16);
+    if (e == hipSuccess) e = ensure_hsmall(c, 4096);
+    for (int i = 0; i < 8 && e == hipSuccess; ++i) e = hipEventCreate(&c->sev[i]);
+    c->hconsts = new EngineConsts();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ckpt_ctx_destroy(c);
+        return e == hipErrorOutOfMemory ? CKPT_ENOMEM : CKPT_EHIP;
+    }
     *out = c;
     return CKPT_OK;
-}
-
-static hipError_t ensure_copy_streams(ckpt_ctx* c, uint32_t n) {
-    while (c->s_copy.size() < n) {
-        hipStream_t s;
-        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
-        c->s_copy.push_back(s);
-    }
-    return hipSuccess;
 }
 
 extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
-    hipStreamSynchronize(c->s_main);
+    if (c->s_main) hipStreamSynchronize(c->s_main);
     for (hipStream_t s : c->s_copy) { hipStreamSynchronize(s); hipStreamDestroy(s); }
-    hipStreamDestroy(c->s_main);
+    if (c->s_main) hipStreamDestroy(c->s_main);
+    if (c->ev_order) hipEventDestroy(c->ev_order);
+    for (hipEvent_t e : c->sev)
+        if (e) hipEventDestroy(e);
+    delete c->hconsts;
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (hipEvent_t e : c->tevents) hipEventDestroy(e);
-    DevBuf* bufs[] = {&c->descs, &c->status, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
+    c->status.release();
+    DevBuf* bufs[] = {&c->descs, &c->ctl, &c->arc, &c->kinds, &c->prevcrc, &c->off, &c->wb,
                       &c->staging, &c->dig, &c->amap, &c->rlen, &c->cmeta};
     for (DevBuf* b : bufs) b->release();
     for (auto& kv : c->consts) kv.second.release();
@@ -510,6 +525,7 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
         if (ge.exec) hipGraphExecDestroy(ge.exec);
         ge.descs.release();
         ge.dig.release();
+        ge.status.release();
     }
     if (c->hsmall) hipHostFree(c->hsmall);
     if (c->hpin) (void)hipHostFree(c->hpin);
@@ -528,11 +544,13 @@ extern "C" void ckpt_ctx_destroy(ckpt_ctx* c) {
 // virtual descriptors; digest_enqueue only launches kernels and one D2H copy
 // (so a captured graph can hold it).
 hipError_t mk::digest_prepare(ckpt_ctx* c, DevBuf* dig, const uint8_t* recs_crc, uint64_t len_a,
-                              const uint8_t* kinds_pad, uint64_t len_b, DigestPlan* p, hipStream_t s) {
+                              const uint8_t* kinds_pad, uint64_t len_b, DigestPlan* p, hipStream_t s,
+                              const EngineConsts* ec) {
     const uint32_t Cd = 16384;
     pick_tile(Cd, 0, &p->T, &p->K);
-    hipError_t e = get_consts(c, p->T, Cd, &p->ec);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (ec) p->ec = ec;
+    else if ((e = get_consts(c, p->T, Cd, &p->ec)) != hipSuccess) return e;
     AllocDesc hd[2];
     const uint64_t nk_a = ceil_div(len_a, Cd), nk_b = ceil_div(len_b, Cd);
     make_desc(&hd[0], 0, recs_crc, len_a, 0, kNoChunk, Cd);
@@ -582,30 +600,39 @@ hipError_t mk::digest_enqueue(ckpt_ctx* c, const DigestPlan& p, uint32_t* out_ho
 }
 
 static int device_table_digests(ckpt_ctx* c, const uint8_t* recs_crc, uint64_t len_a, const uint8_t* kinds_pad,
-                                uint64_t len_b, uint32_t* out_host /* [2], pinned */, ckpt_result* res) {
+                                uint64_t len_b, uint32_t* out_host /* [2], pinned */, ckpt_result* res,
+                                DevBuf* dig = nullptr, const EngineConsts* ec = nullptr) {
     DigestPlan p;
-    HIPCHK(digest_prepare(c, &c->dig, recs_crc, len_a, kinds_pad, len_b, &p, c->s_main));
+    HIPCHK(digest_prepare(c, dig ? dig : &c->dig, recs_crc, len_a, kinds_pad, len_b, &p, c->s_main, ec));
     HIPCHK(digest_enqueue(c, p, out_host, c->s_main));
     return CKPT_OK;
 }
 
 // ------------------------------------------------------------ resident digest tables
-const uint32_t* mk::digest_lookup(ckpt_ctx* c, uint64_t uid, uint64_t nc) {
+const uint32_t* mk::digest_lookup(ckpt_ctx* c, uint64_t uid, uint64_t nc, bool pin) {
     auto it = c->digests.find(uid);
     if (it == c->digests.end() || it->second.n_chunks != nc) return nullptr;
     it->second.last_use = ++c->use_clock;
+    if (pin) it->second.pins++;
     return it->second.crc.as<uint32_t>();
+}
+
+void mk::digest_unpin(ckpt_ctx* c, uint64_t uid) {
+    auto it = c->digests.find(uid);
+    if (it != c->digests.end() && it->second.pins) it->second.pins--;
 }
 
 // Keep an image's digest table resident (copied from crc_dev on stream s;
 // the caller synchronizes s before the table is used).
 void mk::digest_insert(ckpt_ctx* c, uint64_t uid, const uint32_t* crc_dev, uint64_t nc, hipStream_t s) {
     if (!nc) return;
+    if (c->digests.count(uid)) return;   // an image is dumped once; its table never changes
     if (c->digests.size() >= c->digest_capacity) {
-        auto victim = c->digests.begin();
-        for (auto it = c->digests.begin(); it != c->digests.end(); ++it)
-            if (it->second.last_use < victim->second.last_use) victim = it;
-        victim->second.crc.release();
+        // tables pinned by requests in flight are never freed; with every
+        // entry pinned the new table is not kept
+        const uint64_t victim = digest_victim(c->digests, 0);
+        if (!victim) return;
+        c->digests[victim].crc.release();
         c->digests.erase(victim);
     }
     DigestEntry& de = c->digests[uid];
@@ -620,18 +647,53 @@ void mk::digest_insert(ckpt_ctx* c, uint64_t uid, const uint32_t* crc_dev, uint6
 }
 
 // ------------------------------------------------------------ dump
+// Wait for everything the context may have queued, after a failed call: no
+// copy still reads the caller's images and no kernel still writes the
+// caller's allocations once the error is returned.
+static void drain(ckpt_ctx* c) {
+    (void)hipStreamSynchronize(c->s_main);
+    for (hipStream_t s : c->s_copy) (void)hipStreamSynchronize(s);
+    if (c->s_aux) (void)hipStreamSynchronize(c->s_aux);
+    if (c->s_meta) (void)hipStreamSynchronize(c->s_meta);
+    (void)hipGetLastError();   // the error is reported by the return code
+}
+
+
+// Device buffers of one dump: the context's own, or slices of the array.
+struct DumpBufs {
+    DevBuf *descs, *arc, *kinds, *staging, *ctl, *amap, *prevcrc, *off, *wb, *dig, *rlen, *cmeta;
+    StatusBuf* status;
+};
+
+static int dump_run(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+                    const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink, const NaCall* na);
+
 int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
-              const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink) {
+                  const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink) {
+    const int rc = dump_run(c, table, prev, out, o, stream, res, sink, nullptr);
+    if (rc != CKPT_OK) drain(c);
+    return rc;
+}
+
+// Per-window bookkeeping (ticket, payload total, its host copy, events) is
+// kept on a ring of kRing entries: window w + kRing is launched only after
+// the host has waited for window w, so any number of windows needs a fixed
+// set of buffers and events.
+constexpr uint64_t kRing = 4;
+
+static int dump_run(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, ckpt_image** out,
+                    const ckpt_opts* o, void* stream, ckpt_result* res, PayloadSink* sink, const NaCall* na) {
     const uint64_t t_start = now_ns();
     const uint32_t C = (o && o->chunk_size) ? o->chunk_size : kDefaultChunk;
     if (!valid_chunk(C)) return CKPT_EINVAL;
-    if (o && (o->reserved ||
-              (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING | CKPT_OPT_CODEC))))
+    if (o && (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING | CKPT_OPT_CODEC)))
         return CKPT_EINVAL;
     const bool codec = o && (o->flags & CKPT_OPT_CODEC);
     if (codec && (!codec_chunk_supported(C) || (o->flags & (CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH)))) return CKPT_EINVAL;
+    if (na && ((o && (o->flags & (CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_CODEC))) || sink)) return CKPT_EINVAL;
     const uint32_t n = table->n;
     if (n && !table->v) return CKPT_EINVAL;
+    if (na && n > kNaMaxAllocs) return CKPT_ELIMIT;
     {
         std::unordered_set<uint64_t> ids;
         ids.reserve(n * 2 + 1);
@@ -645,10 +707,11 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     ImageView pv;
     std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> prev_map;   // id -> (size, first)
     if (prev) {
-        int rc = parse_image(prev->p, prev->n, &pv, false);
+        // the whole structure, tables digest included: the UNCHANGED kinds
+        // rest on prev's digest table
+        int rc = parse_image(prev->p, prev->n, &pv, true);
         if (rc) return rc;
         if (pv.C != C) return CKPT_EINVAL;
-        pv.state_digest = host_crc32c(pv.recs, 32ull * pv.n_allocs + 4 * pv.n_chunks);
         prev_map.reserve(pv.n_allocs * 2 + 1);
         for (uint64_t a = 0; a < pv.n_allocs; ++a)
             prev_map.emplace(get64(pv.recs + 32 * a), std::make_pair(get64(pv.recs + 32 * a + 8),
@@ -671,6 +734,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         if (nk) upper += (nk - 1) * C + round16(d[a].tail_len);
     }
     const uint64_t nc = g;
+    if (na && (nc > kNaMaxChunks || (prev && pv.n_chunks > kNaMaxChunks))) return CKPT_ELIMIT;
     const uint64_t tl = tables_len(n, nc, codec);
     const uint64_t rl_bytes = codec ? 4 * nc : 0;   // the record-length table of the codec layout
     const bool per_alloc = o && (o->flags & CKPT_OPT_PER_ALLOC);
@@ -678,58 +742,123 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     pick_tile(C, o ? o->wg_threads : 0, &T, &K);
     uint64_t slot;
     int nslots;
-    pick_staging(c, o, nc, C, &slot, &nslots);
+    if (na) {
+        // the array's two staging slots, each holding whole chunks (at most
+        // as many as there are look-back words)
+        const uint64_t per = std::min<uint64_t>(kNaSlot / C, kNaStatusWords - 64);
+        if (per == 0) return CKPT_ELIMIT;
+        slot = per * C;
+        nslots = ceil_div(std::max<uint64_t>(nc, 1), per) > 1 ? 2 : 1;
+    } else {
+        pick_staging(c, o, nc, C, &slot, &nslots);
+    }
     std::vector<Window> wins = plan_windows(d, nc, C, slot, per_alloc);
-    const uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
-    if ((uint64_t)nslots * slot > c->budget && nslots > 1) return CKPT_ENOMEM;
+    uint32_t ncs = (o && o->copy_streams) ? o->copy_streams : 2;
+    if (na) ncs = std::min<uint32_t>(ncs, (uint32_t)c->s_copy.size());   // streams made with the context
+    if (!na && (uint64_t)nslots * slot > c->budget && nslots > 1) return CKPT_ENOMEM;
 
+    // device buffers: the context's own, or slices of the static array
+    DevBuf na_bufs[9];
+    DumpBufs B = {&c->descs, &c->arc, &c->kinds, &c->staging, &c->ctl, &c->amap, &c->prevcrc, &c->off, &c->wb,
+                  &c->dig, &c->rlen, &c->cmeta, &c->status};
+    if (na) {
+        uint8_t* base = na->dev->ptr;
+        na_bufs[0].attach(base + kNaDescs, 64ull * kNaMaxAllocs);
+        na_bufs[1].attach(base + kNaArc, kNaTables);
+        na_bufs[2].attach(base + kNaKinds, kNaTables);
+        na_bufs[3].attach(base + kNaStaging, 2 * kNaSlot);
+        na_bufs[4].attach(base + kNaCtl, 64 << 10);
+        na_bufs[5].attach(base + kNaAmap, 4 * kNaMaxChunks);
+        na_bufs[6].attach(base + kNaPrev, 4 * kNaMaxChunks);
+        na_bufs[7].attach(base + kNaDig, 64 << 10);
+        B = {&na_bufs[0], &na_bufs[1], &na_bufs[2], &na_bufs[3], &na_bufs[4], &na_bufs[5], &na_bufs[6], &na_bufs[8],
+             &na_bufs[8], &na_bufs[7], &na_bufs[8], &na_bufs[8], &na->dev->status};   // [8]: empty, never used
+    }
+
+    const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(ensure_copy_streams(c, ncs));
+    if (!na) HIPCHK(ensure_copy_streams(c, ncs));
     HIPCHK(order_after(c, stream));
-    // device buffers
-    HIPCHK(c->descs.ensure(sizeof(AllocDesc) * std::max<uint32_t>(n, 1)));
-    HIPCHK(c->arc.ensure(tl + 16));
-    HIPCHK(c->kinds.ensure(tl + 16));
-    HIPCHK(c->staging.ensure((uint64_t)nslots * slot));
+    // stage events: [0, 1] set-up, [2, 3] finalize, [4] classify end, [5] scan end
+    if (timing) HIPCHK(hipEventRecord(c->sev[0], c->s_main));
+    HIPCHK(B.descs->ensure(sizeof(AllocDesc) * std::max<uint32_t>(n, 1)));
+    HIPCHK(B.arc->ensure(tl + 16));
+    HIPCHK(B.kinds->ensure(tl + 16));
+    HIPCHK(B.staging->ensure((uint64_t)nslots * slot));
     uint64_t max_win = 1;
     for (const Window& w : wins) max_win = std::max(max_win, w.g1 - w.g0);
-    HIPCHK(c->status.ensure(8 * (max_win + 64)));
+    if (na && !na->dev->cleared) {
+        // the array's look-back words, once per device: any words at all may be there
+        HIPCHK(launch_fill64(B.status->words(), 0, kNaStatusWords, c->s_main));
+        na->dev->cleared = true;
+    }
+    HIPCHK(B.status->ensure(8 * (max_win + 64), c->s_main));
     const uint64_t W = wins.size();
-    // ctl: tickets[max(W, 3, codec pieces + 2) + 1] | wtot[W + 1] (u64) | err (+pad) | counts[4] (u64)
-    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(W, 3), codec ? 2 * kCodecPieces + 2 : 0) + 1;
-    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (n_tk + 1)),
-                   ctl_err = ctl_wt + 8 * (W + 1), ctl_cnt = ctl_err + 16;
-    HIPCHK(c->ctl.ensure(ctl_err + 64));
-    HIPCHK(ensure_hsmall(c, 8 * (W + 1) + 64));
     const uint64_t codec_p = codec ? (W == 1 ? std::min<uint64_t>(kCodecPieces, nc) : W) : 0;   // codec pieces
-    HIPCHK(ensure_events(c, std::max<size_t>(W + (size_t)nslots + 2, 4 * codec_p + 1)));
-    const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * std::max<uint64_t>(W, 2 * codec_p)));
+    // ctl: tickets[n_tk] | wtot[kRing + 1] (u64) | err (+pad) | counts[4] (u64); window tickets and
+    // totals on the ring, codec pieces' tickets by piece
+    const uint64_t n_tk = std::max<uint64_t>(std::max<uint64_t>(kRing, 2 * kCodecPieces + 2), codec_p) + 1;
+    const uint64_t ctl_tk = 0, ctl_wt = round16(4 * (n_tk + 1)),
+                   ctl_err = ctl_wt + 8 * (kRing + 1), ctl_cnt = ctl_err + 16;
+    HIPCHK(B.ctl->ensure(ctl_err + 64));
+    HIPCHK(ensure_hsmall(c, 8 * (kRing + 1) + 64 + 8 * kCodecPieces));   // ring totals, digests, piece lengths
+    // events: [0, kRing) window done, [kRing, kRing + nslots) slot free; codec pieces: 4 per piece
+    HIPCHK(ensure_events(c, std::max<size_t>(std::max<size_t>(kRing + (size_t)nslots + 2, 4 * codec_p + 1),
+                                             kCodecPieces + 1)));
+    if (timing) HIPCHK(ensure_tevents(c, std::max<uint64_t>(2 * std::max<uint64_t>(kRing, 2 * codec_p), 4 * kCodecPieces)));
     const EngineConsts* ec;
-    HIPCHK(get_consts(c, T, C, &ec));
+    const EngineConsts* dig_ec = nullptr;   // table-digest engine constants (array slice), or the cache's
+    if (na) {
+        // engine constants in the array, rebuilt when the tile or chunk size
+        // changes (host build space of the context; the copy completes before
+        // the space is reused)
+        NaDevice& nd = *na->dev;
+        if (nd.T != T || nd.C != C) {
+            build_engine_consts(c->hconsts, T, C);
+            HIPCHK(hipMemcpyAsync(nd.ptr + kNaConsts, c->hconsts, sizeof(EngineConsts), hipMemcpyHostToDevice,
+                                  c->s_main));
+            HIPCHK(hipStreamSynchronize(c->s_main));
+            nd.T = T;
+            nd.C = C;
+        }
+        if (!nd.dconsts) {
+            int dT, dK;
+            pick_tile(16384, 0, &dT, &dK);
+            build_engine_consts(c->hconsts, dT, 16384);
+            HIPCHK(hipMemcpyAsync(nd.ptr + kNaDConsts, c->hconsts, sizeof(EngineConsts), hipMemcpyHostToDevice,
+                                  c->s_main));
+            HIPCHK(hipStreamSynchronize(c->s_main));
+            nd.dconsts = true;
+        }
+        ec = reinterpret_cast<const EngineConsts*>(nd.ptr + kNaConsts);
+        dig_ec = reinterpret_cast<const EngineConsts*>(nd.ptr + kNaDConsts);
+    } else {
+        HIPCHK(get_consts(c, T, C, &ec));
+    }
 
     // resident digest table of the previous image
     const uint32_t* prev_dev = nullptr;
     if (prev && pv.n_chunks) {
         prev_dev = digest_lookup(c, prev->uid, pv.n_chunks);
         if (!prev_dev) {
-            HIPCHK(c->prevcrc.ensure(4 * pv.n_chunks));
-            HIPCHK(hipMemcpyAsync(c->prevcrc.p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, c->s_main));
-            prev_dev = c->prevcrc.as<uint32_t>();
+            HIPCHK(B.prevcrc->ensure(4 * pv.n_chunks));
+            HIPCHK(hipMemcpyAsync(B.prevcrc->p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, c->s_main));
+            prev_dev = B.prevcrc->as<uint32_t>();
         }
     }
 
-    uint8_t* ctl = c->ctl.as<uint8_t>();
+    uint8_t* ctl = B.ctl->as<uint8_t>();
     uint32_t* tickets = reinterpret_cast<uint32_t*>(ctl + ctl_tk);
     uint64_t* wtot = reinterpret_cast<uint64_t*>(ctl + ctl_wt);
     uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctl + ctl_cnt);
-    HIPCHK(c->amap.ensure(4 * std::max<uint64_t>(nc, 1)));
-    HIPCHK(hipMemcpyAsync(c->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice, c->s_main));
-    HIPCHK(launch_chunk_map(c->descs.as<AllocDesc>(), n, C, c->amap.as<uint32_t>(), c->s_main));
+    HIPCHK(B.amap->ensure(4 * std::max<uint64_t>(nc, 1)));
+    HIPCHK(hipMemcpyAsync(B.descs->p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice, c->s_main));
+    HIPCHK(launch_chunk_map(B.descs->as<AllocDesc>(), n, C, B.amap->as<uint32_t>(), c->s_main));
     HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (ctl_err + 64) / 4, c->s_main));
     // kinds buffer: zero padding after the kinds (the kinds themselves are written by the kernel)
-    HIPCHK(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
+    HIPCHK(launch_fill32(B.kinds->as<uint32_t>(), 0, ceil_div(tl - 32ull * n - 4 * nc, 4), c->s_main));
+    if (timing) HIPCHK(hipEventRecord(c->sev[1], c->s_main));
 
     // With one staging slot and several windows (per-allocation launches
     // when the whole image fits the staging budget) each window's payload is
@@ -741,12 +870,22 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     // bound; pinned host memory is limited)
     ckpt_image* im = nullptr;
     uint8_t* himg = nullptr;
-    if (W > 1 && !stage_all) {
+    ckpt_image na_img;   // the caller's buffer (no-allocation dump)
+    if (na) {
+        if (na->cap < kHeader + tl) return CKPT_ENOMEM;
+        na_img.p = na->out;
+        na_img.cap = na->cap;
+        na_img.pinned = false;
+        im = &na_img;
+        himg = na->out;
+    } else if (W > 1 && !stage_all) {
         im = image_new(kHeader + tl + upper);
         if (!im) return CKPT_ENOMEM;
         himg = im->p;
         if (sink) sink->begin(im);
     }
+    // the image can take a payload of D bytes (the caller's buffer is fixed)
+    auto fits = [&](uint64_t D) { return !na || kHeader + tl + D <= na->cap; };
     // payload bytes [pay, pay + len) of the image from device memory, on
     // stream s; with a sink, in segments it is told about one by one
     auto copy_out = [&](uint64_t pay, const uint8_t* src, uint64_t len, hipStream_t s) -> hipError_t {
@@ -760,7 +899,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         return hipSuccess;
     };
     auto alloc_image = [&](uint64_t D) -> bool {
-        if (im) return true;
+        if (im) return fits(D);
         im = image_new(kHeader + tl + D);
         if (!im) return false;
         himg = im->p;
@@ -768,9 +907,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         return true;
     };
     uint64_t* hw = reinterpret_cast<uint64_t*>(c->hsmall);
-    uint32_t* crc_dev = reinterpret_cast<uint32_t*>(c->arc.as<uint8_t>() + 32ull * n);
-    uint8_t* kind_dev = c->kinds.as<uint8_t>();
-    std::vector<hipEvent_t>& ev = c->events;   // [0, W): window done; [W, W+nslots): slot free
+    uint32_t* crc_dev = reinterpret_cast<uint32_t*>(B.arc->as<uint8_t>() + 32ull * n);
+    uint8_t* kind_dev = B.kinds->as<uint8_t>();
+    std::vector<hipEvent_t>& ev = c->events;   // [0, kRing): window done (ring); [kRing, kRing + nslots): slot free
     std::vector<bool> slot_used(nslots, false);
     auto fail = [&](hipError_t e) {
         hipStreamSynchronize(c->s_main);
@@ -779,7 +918,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         for (uint32_t i = 0; i < ncs; ++i) hipStreamSynchronize(c->s_copy[i]);
         (void)hipGetLastError();   // the error is reported by the return code
         if (sink) sink->end();     // nothing reads the image after this
-        if (im) image_release(im);
+        if (im && !na) image_release(im);
         if (e == hipErrorOutOfMemory) return CKPT_ENOMEM;
         if (res) res->hip_error = (int32_t)e;
         return CKPT_EHIP;
@@ -787,132 +926,189 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
 
     auto launch_window = [&](uint64_t w, uint64_t base) -> hipError_t {
         const int s = (int)(w % nslots);
+        const uint64_t q = w % kRing;
         hipError_t e;
         if (slot_used[s] && !stage_all) {
-            e = hipStreamWaitEvent(c->s_main, ev[W + s], 0);
+            e = hipStreamWaitEvent(c->s_main, ev[kRing + s], 0);
             if (e != hipSuccess) return e;
         }
         slot_used[s] = true;
-        bool wrapped;
-        const uint32_t ep = next_epoch(c, &wrapped);
-        if (wrapped) {
-            e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main);
-            if (e != hipSuccess) return e;
-        }
+        // the ring entry's ticket was used by window w - kRing, which the
+        // host has waited for
+        if (w >= kRing && (e = launch_fill32(tickets + q, 0, 1, c->s_main)) != hipSuccess) return e;
+        uint32_t ep;
+        if ((e = B.status->next(c->s_main, &ep)) != hipSuccess) return e;
         ChunkJob j;
         memset(&j, 0, sizeof(j));
-        j.allocs = c->descs.as<AllocDesc>();
+        j.allocs = B.descs->as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
-        j.amap = c->amap.as<uint32_t>();
+        j.amap = B.amap->as<uint32_t>();
         j.g0 = wins[w].g0;
         j.g1 = wins[w].g1;
         j.ec = ec;
         j.crc_out = crc_dev;
         j.kind_out = kind_dev;
         j.prev_crc = prev_dev;
-        j.slot = c->staging.as<uint8_t>() + (stage_all ? base : (uint64_t)s * slot);
-        j.status = c->status.as<uint64_t>();
-        j.wtotal = wtot + w;
+        j.slot = B.staging->as<uint8_t>() + (stage_all ? base : (uint64_t)s * slot);
+        j.status = B.status->words();
+        j.wtotal = wtot + q;
         j.err = err;
         j.epoch = ep;
         int grid;
         e = grid_for(c, T, K, kModeDump, j.g1 - j.g0, &grid);
         if (e != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[2 * w], c->s_main)) != hipSuccess) return e;
-        e = launch_chunks(T, K, kModeDump, one_job(j, tickets + w), grid, c->s_main);
+        if (timing && (e = hipEventRecord(c->tevents[2 * q], c->s_main)) != hipSuccess) return e;
+        e = launch_chunks(T, K, kModeDump, one_job(j, tickets + q), grid, c->s_main);
         if (e != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[2 * w + 1], c->s_main)) != hipSuccess) return e;
-        e = hipMemcpyAsync(hw + w, wtot + w, 8, hipMemcpyDeviceToHost, c->s_main);
+        if (timing && (e = hipEventRecord(c->tevents[2 * q + 1], c->s_main)) != hipSuccess) return e;
+        e = hipMemcpyAsync(hw + q, wtot + q, 8, hipMemcpyDeviceToHost, c->s_main);
         if (e != hipSuccess) return e;
-        return hipEventRecord(ev[w], c->s_main);
+        return hipEventRecord(ev[q], c->s_main);
     };
 
-    uint64_t pos = 0, t_link0 = 0;
+    uint64_t pos = 0, t_link0 = 0, kern_ns = 0;
     hipError_t e = hipSuccess;
     const uint64_t len_a = 32ull * n + 4 * nc, len_b = tl - len_a - rl_bytes;
-    uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall + 8 * (W + 1));
+    uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall + 8 * (kRing + 1));
     const bool use_graph = o && (o->flags & CKPT_OPT_GRAPH) && W == 1 && !per_alloc;
-    // A delta dump in one window takes three passes: digests and kinds of
-    // every chunk, the payload offsets (scan over the kinds), then the DATA
-    // chunks gathered to their records. A delta's kinds depend on the
+    // A delta dump in one window takes three passes per piece (launch_delta):
+    // digests and kinds, the payload offsets (scan over the kinds), then the
+    // DATA chunks gathered to their records. A delta's kinds depend on the
     // digests, so a single pass would hold every chunk's look-back until its
     // digest is done; its payload is small, so the extra read of D costs
     // little.
-    const bool two_pass = prev != nullptr && W == 1 && !use_graph && nc > 0;
+    const bool two_pass = prev != nullptr && W == 1 && !use_graph && nc > 0 && !na;
+    uint64_t delta_pieces = 0;
     // the DATA chunks of [g0, g1) to their records at c->off, in staging
     // from sp on, which holds the payload from offset base
     auto gather_job = [&](uint64_t g0, uint64_t g1, uint8_t* sp, uint64_t base) {
         GatherJob gj;
         memset(&gj, 0, sizeof(gj));
-        gj.allocs = c->descs.as<AllocDesc>();
-        gj.amap = c->amap.as<uint32_t>();
+        gj.allocs = B.descs->as<AllocDesc>();
+        gj.amap = B.amap->as<uint32_t>();
         gj.g0 = g0;
         gj.g1 = g1;
         gj.C = C;
         gj.kind = kind_dev;
-        gj.off = c->off.as<uint64_t>();
+        gj.off = B.off->as<uint64_t>();
         gj.slot = sp;
         gj.slot_base = base;
         return gj;
     };
-    auto launch_two_pass = [&]() -> hipError_t {
+    // The delta dump in one window runs as a pipeline over kCodecPieces pieces
+    // of equal chunk counts. On the main stream, per piece: digests and kinds
+    // (classify), the piece's payload offsets relative to its own start (scan)
+    // and its DATA chunks gathered into its own part of staging (from its
+    // first chunk's bound g0 C on); the piece's payload length comes back to
+    // the host, which places the piece after the earlier ones and queues its
+    // copy-out while the main stream works on later pieces. The image is
+    // allocated once the first piece's length is known, at that length scaled
+    // to all chunks plus a margin: a delta's only firm bound is the whole
+    // state, which would hold that much pinned memory for a small image. A
+    // payload that outgrows the estimate moves, with what was copied so far,
+    // to an image of the bound (with a file sink, the bound from the start).
+    // Returns the payload length in *D_out.
+    auto launch_delta = [&](uint64_t* D_out) -> hipError_t {
         hipError_t e;
-        bool wrapped;
-        const uint32_t ep = next_epoch(c, &wrapped);
-        if (wrapped && (e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main)) != hipSuccess)
-            return e;
-        if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
-        if ((e = c->wb.ensure(16)) != hipSuccess) return e;
-        ChunkJob j;
-        memset(&j, 0, sizeof(j));
-        j.allocs = c->descs.as<AllocDesc>();
-        j.n_allocs = n;
-        j.C = C;
-        j.amap = c->amap.as<uint32_t>();
-        j.g0 = 0;
-        j.g1 = nc;
-        j.ec = ec;
-        j.crc_out = crc_dev;
-        j.kind_out = kind_dev;
-        j.kind_in = kind_dev;
-        j.prev_crc = prev_dev;
-        j.slot = c->staging.as<uint8_t>();
-        j.off = c->off.as<uint64_t>();
-        j.slot_base = 0;
-        j.err = err;
-        j.epoch = ep;
-        int grid;
-        if ((e = grid_for(c, T, K, kModeClassify, nc, &grid)) != hipSuccess) return e;
-        if (timing && (e = hipEventRecord(c->tevents[0], c->s_main)) != hipSuccess) return e;
-        if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 0), grid, c->s_main)) != hipSuccess) return e;
-        OffJob oj;
-        memset(&oj, 0, sizeof(oj));
-        oj.allocs = c->descs.as<AllocDesc>();
-        oj.n_allocs = n;
-        oj.C = C;
-        oj.amap = c->amap.as<uint32_t>();
-        oj.n_chunks = nc;
-        oj.kind = kind_dev;
-        oj.off = c->off.as<uint64_t>();
-        oj.per_window = nc + 1;
-        oj.wb = c->wb.as<uint64_t>();
-        oj.n_windows = 1;
-        oj.status = c->status.as<uint64_t>();
-        oj.ticket = tickets + 1;
-        oj.counts = counts;
-        oj.err = err;
-        oj.epoch = ep;
-        const uint64_t tiles = ceil_div(nc, 256);
-        if ((e = launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main)) != hipSuccess)
-            return e;
-        if ((e = launch_gather(gather_job(0, nc, c->staging.as<uint8_t>(), 0), pack_grid(c, nc), c->s_main)) !=
-            hipSuccess)
-            return e;
-        if (timing && (e = hipEventRecord(c->tevents[1], c->s_main)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(hw, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
-            return e;
-        return hipEventRecord(ev[0], c->s_main);
+        const uint64_t P = std::min<uint64_t>(kCodecPieces, nc);
+        if ((e = B.off->ensure(8 * nc)) != hipSuccess) return e;
+        if ((e = B.wb->ensure(16 * P)) != hipSuccess) return e;
+        uint64_t* htot = reinterpret_cast<uint64_t*>(c->hsmall + 8 * (kRing + 1) + 64);   // [P] piece lengths
+        std::vector<uint64_t> gb(P + 1);
+        for (uint64_t i = 0; i <= P; ++i) gb[i] = nc * i / P;
+        for (uint64_t i = 0; i < P; ++i) {
+            const uint64_t g0 = gb[i], g1 = gb[i + 1];
+            uint32_t ep;
+            if ((e = B.status->next(c->s_main, &ep)) != hipSuccess) return e;
+            ChunkJob j;
+            memset(&j, 0, sizeof(j));
+            j.allocs = B.descs->as<AllocDesc>();
+            j.n_allocs = n;
+            j.C = C;
+            j.amap = B.amap->as<uint32_t>();
+            j.g0 = g0;
+            j.g1 = g1;
+            j.ec = ec;
+            j.crc_out = crc_dev;
+            j.kind_out = kind_dev;
+            j.prev_crc = prev_dev;
+            j.err = err;
+            j.epoch = ep;
+            int grid;
+            if ((e = grid_for(c, T, K, kModeClassify, g1 - g0, &grid)) != hipSuccess) return e;
+            if (timing && (e = hipEventRecord(c->tevents[4 * i], c->s_main)) != hipSuccess) return e;
+            if ((e = launch_chunks(T, K, kModeClassify, one_job(j, tickets + 2 * i), grid, c->s_main)) != hipSuccess)
+                return e;
+            if (timing && (e = hipEventRecord(c->tevents[4 * i + 1], c->s_main)) != hipSuccess) return e;
+            OffJob oj;
+            memset(&oj, 0, sizeof(oj));
+            oj.allocs = B.descs->as<AllocDesc>();
+            oj.n_allocs = n;
+            oj.C = C;
+            oj.amap = B.amap->as<uint32_t>();
+            oj.n_chunks = g1 - g0;
+            oj.g_base = g0;
+            oj.kind = kind_dev;
+            oj.off = B.off->as<uint64_t>();
+            oj.per_window = g1 - g0 + 1;
+            oj.wb = B.wb->as<uint64_t>() + 2 * i;
+            oj.n_windows = 1;
+            oj.status = B.status->words();
+            oj.ticket = tickets + 2 * i + 1;
+            oj.counts = counts;
+            oj.err = err;
+            oj.epoch = ep;
+            const uint64_t tiles = ceil_div(g1 - g0, 256);
+            if ((e = launch_offsets(oj, (int)std::min<uint64_t>(tiles, 8ull * c->num_cu), c->s_main)) != hipSuccess)
+                return e;
+            if (timing && (e = hipEventRecord(c->tevents[4 * i + 2], c->s_main)) != hipSuccess) return e;
+            uint8_t* sp = B.staging->as<uint8_t>() + g0 * C;
+            if ((e = launch_gather(gather_job(g0, g1, sp, 0), pack_grid(c, g1 - g0), c->s_main)) != hipSuccess)
+                return e;
+            if (timing && (e = hipEventRecord(c->tevents[4 * i + 3], c->s_main)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(htot + i, B.wb->as<uint64_t>() + 2 * i + 1, 8, hipMemcpyDeviceToHost,
+                                    c->s_main)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(ev[i], c->s_main)) != hipSuccess) return e;
+        }
+        uint64_t D = 0, cap = 0;   // payload so far; payload capacity of the image
+        for (uint64_t i = 0; i < P; ++i) {
+            const uint64_t g0 = gb[i], g1 = gb[i + 1];
+            if ((e = hipEventSynchronize(ev[i])) != hipSuccess) return e;
+            const uint64_t Di = htot[i];
+            if (Di > (g1 - g0) * C || D + Di > upper) return hipErrorIllegalState;
+            if (!im) {
+                const uint64_t est = sink ? upper
+                                          : std::min<uint64_t>(upper, ceil_div(Di * nc, g1 - g0) + Di / 4 + (64ull << 20));
+                im = image_new(kHeader + tl + est);
+                if (!im) return hipErrorOutOfMemory;
+                himg = im->p;
+                cap = est;
+                if (sink) sink->begin(im);
+            } else if (D + Di > cap) {
+                // outgrown: an image of the bound, with the payload copied so far
+                for (uint32_t k = 0; k < ncs; ++k)
+                    if ((e = hipStreamSynchronize(c->s_copy[k])) != hipSuccess) return e;
+                ckpt_image* big = image_new(kHeader + tl + upper);
+                if (!big) return hipErrorOutOfMemory;
+                memcpy(big->p + kHeader + tl, himg + kHeader + tl, D);
+                image_release(im);
+                im = big;
+                himg = im->p;
+                cap = upper;
+            }
+            if (Di) {
+                hipStream_t cs = c->s_copy[i % ncs];
+                if (!t_link0) t_link0 = now_ns();
+                if ((e = hipStreamWaitEvent(cs, ev[i], 0)) != hipSuccess) return e;
+                if ((e = copy_out(D, B.staging->as<uint8_t>() + g0 * C, Di, cs)) != hipSuccess) return e;
+            }
+            D += Di;
+        }
+        delta_pieces = P;
+        *D_out = D;
+        return hipSuccess;
     };
     // Codec dump in pieces: in one window kCodecPieces pieces of equal chunk
     // counts, else one piece per staging window (on the slot ring; a piece
@@ -931,13 +1127,11 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     uint64_t codec_pairs = 0;
     auto launch_codec = [&](uint64_t* D_out) -> hipError_t {
         hipError_t e;
-        bool wrapped;
-        const uint32_t ep = next_epoch(c, &wrapped);
-        if (wrapped && (e = launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main)) != hipSuccess)
-            return e;
-        if ((e = c->off.ensure(8 * nc)) != hipSuccess) return e;
-        if ((e = c->rlen.ensure(4 * nc)) != hipSuccess) return e;
-        if ((e = c->cmeta.ensure((uint64_t)kPackMeta * nc)) != hipSuccess) return e;
+        uint32_t ep;
+        if ((e = B.status->next(c->s_main, &ep)) != hipSuccess) return e;
+        if ((e = B.off->ensure(8 * nc)) != hipSuccess) return e;
+        if ((e = B.rlen->ensure(4 * nc)) != hipSuccess) return e;
+        if ((e = B.cmeta->ensure((uint64_t)kPackMeta * nc)) != hipSuccess) return e;
         if ((e = ensure_hpin(c, 12 * nc)) != hipSuccess) return e;
         if (!c->s_aux && (e = hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
         if (!c->s_meta && (e = hipStreamCreateWithFlags(&c->s_meta, hipStreamNonBlocking)) != hipSuccess) return e;
@@ -947,31 +1141,31 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         if (!alloc_image(upper)) return hipErrorOutOfMemory;
         ChunkJob j;
         memset(&j, 0, sizeof(j));
-        j.allocs = c->descs.as<AllocDesc>();
+        j.allocs = B.descs->as<AllocDesc>();
         j.n_allocs = n;
         j.C = C;
-        j.amap = c->amap.as<uint32_t>();
+        j.amap = B.amap->as<uint32_t>();
         j.ec = ec;
         j.crc_out = crc_dev;
         j.kind_out = kind_dev;
         j.kind_in = kind_dev;
         j.prev_crc = prev_dev;
-        j.slot = c->staging.as<uint8_t>();
-        j.off = c->off.as<uint64_t>();
+        j.slot = B.staging->as<uint8_t>();
+        j.off = B.off->as<uint64_t>();
         j.slot_base = 0;
         j.err = err;
         j.epoch = ep;
         PackJob pj;
         memset(&pj, 0, sizeof(pj));
-        pj.allocs = c->descs.as<AllocDesc>();
-        pj.amap = c->amap.as<uint32_t>();
+        pj.allocs = B.descs->as<AllocDesc>();
+        pj.amap = B.amap->as<uint32_t>();
         pj.C = C;
         pj.kind = kind_dev;
-        pj.rlen = c->rlen.as<uint32_t>();
-        pj.off = c->off.as<uint64_t>();
-        pj.slot = c->staging.as<uint8_t>();
+        pj.rlen = B.rlen->as<uint32_t>();
+        pj.off = B.off->as<uint64_t>();
+        pj.slot = B.staging->as<uint8_t>();
         pj.err = err;
-        pj.meta = c->cmeta.as<uint8_t>();
+        pj.meta = B.cmeta->as<uint8_t>();
         const bool one = W == 1;
         const uint64_t P = codec_p;
         std::vector<uint64_t> gb(P + 1);
@@ -1006,9 +1200,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             }
             // records never exceed their chunks (nor a window its slot)
             if (D > upper || (one ? D : D - lo) > slot) return hipErrorIllegalState;
-            uint8_t* sp = c->staging.as<uint8_t>() + (one ? 0 : (i % nslots) * slot);
+            uint8_t* sp = B.staging->as<uint8_t>() + (one ? 0 : (i % nslots) * slot);
             const uint64_t base = one ? 0 : lo;
-            if (g1 > g0 && (e = hipMemcpyAsync(c->off.as<uint64_t>() + g0, off_h + g0, 8 * (g1 - g0),
+            if (g1 > g0 && (e = hipMemcpyAsync(B.off->as<uint64_t>() + g0, off_h + g0, 8 * (g1 - g0),
                                                hipMemcpyHostToDevice, c->s_meta)) != hipSuccess)
                 return e;
             if ((e = hipEventRecord(ev[P + i], c->s_meta)) != hipSuccess) return e;
@@ -1051,8 +1245,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
         mix(n); mix(C); mix((uint64_t)T); mix((uint64_t)K); mix(nc);
         for (const AllocDesc& x : d) { mix(x.id); mix(x.ptr); mix(x.size); mix(x.prev_first); }
-        const void* ptrs[] = {prev_dev, c->arc.p, c->kinds.p, c->status.p, c->staging.p, c->ctl.p, c->hsmall, ec,
-                              c->amap.p};
+        const void* ptrs[] = {prev_dev, B.arc->p, B.kinds->p, B.staging->p, B.ctl->p, c->hsmall, ec, B.amap->p};
         for (const void* q : ptrs) mix(reinterpret_cast<uint64_t>(q));
         GraphEntry* ge = nullptr;
         for (auto& x : c->graphs)
@@ -1066,46 +1259,49 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
                 if (victim->exec) hipGraphExecDestroy(victim->exec);
                 victim->descs.release();
                 victim->dig.release();
+                victim->status.release();
                 c->graphs.erase(victim);
             }
             c->graphs.emplace_back();
             ge = &c->graphs.back();
             ge->key = key;
             if ((e = ge->descs.ensure(sizeof(AllocDesc) * std::max<uint32_t>(n, 1))) != hipSuccess) return fail(e);
+            if ((e = ge->status.ensure(8 * (nc + 64))) != hipSuccess) return fail(e);
             if ((e = hipMemcpy(ge->descs.p, d.data(), sizeof(AllocDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
                 return fail(e);
             DigestPlan dp;
-            if ((e = digest_prepare(c, &ge->dig, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, &dp, c->s_main)) != hipSuccess)
+            if ((e = digest_prepare(c, &ge->dig, B.arc->as<uint8_t>(), len_a, kind_dev, len_b, &dp, c->s_main)) != hipSuccess)
                 return fail(e);
             int grid, gd;
             if ((e = grid_for(c, T, K, kModeDump, nc, &grid)) != hipSuccess) return fail(e);
             if ((e = grid_for(c, dp.T, dp.K, kModeDigest, std::max<uint64_t>(dp.nk, 1), &gd)) != hipSuccess) return fail(e);
             if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
-            bool wrapped;
-            const uint32_t ep = next_epoch(c, &wrapped);
+            // every replay clears the graph's own look-back words first, so
+            // one epoch serves all replays
+            const uint32_t ep = 1;
             hipGraph_t graph = nullptr;
             if ((e = hipStreamBeginCapture(c->s_main, hipStreamCaptureModeThreadLocal)) != hipSuccess) return fail(e);
             hipError_t ce = hipSuccess;
             auto step = [&ce](hipError_t r) { if (ce == hipSuccess) ce = r; };
             // every replay clears what must start at zero with fill kernels
             step(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (ctl_err + 64) / 4, c->s_main));
-            step(launch_fill32(c->kinds.as<uint32_t>(), 0, ceil_div(len_b, 4), c->s_main));
-            step(launch_fill64(c->status.as<uint64_t>(), 0, nc + 64, c->s_main));
-            step(launch_chunk_map(ge->descs.as<AllocDesc>(), n, C, c->amap.as<uint32_t>(), c->s_main));
+            step(launch_fill32(B.kinds->as<uint32_t>(), 0, ceil_div(len_b, 4), c->s_main));
+            step(launch_fill64(ge->status.as<uint64_t>(), 0, nc + 64, c->s_main));
+            step(launch_chunk_map(ge->descs.as<AllocDesc>(), n, C, B.amap->as<uint32_t>(), c->s_main));
             ChunkJob j;
             memset(&j, 0, sizeof(j));
             j.allocs = ge->descs.as<AllocDesc>();
             j.n_allocs = n;
             j.C = C;
-            j.amap = c->amap.as<uint32_t>();
+            j.amap = B.amap->as<uint32_t>();
             j.g0 = 0;
             j.g1 = nc;
             j.ec = ec;
             j.crc_out = crc_dev;
             j.kind_out = kind_dev;
             j.prev_crc = prev_dev;
-            j.slot = c->staging.as<uint8_t>();
-            j.status = c->status.as<uint64_t>();
+            j.slot = B.staging->as<uint8_t>();
+            j.status = ge->status.as<uint64_t>();
             j.wtotal = wtot;
             j.err = err;
             j.epoch = ep;
@@ -1118,7 +1314,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             gcj.C = C;
             gcj.crc = crc_dev;
             gcj.ec = ec;
-            gcj.recs = c->arc.as<uint8_t>();
+            gcj.recs = B.arc->as<uint8_t>();
             gcj.mode = kCombineWrite;
             step(launch_combine(gcj, c->s_main));
             step(digest_enqueue(c, dp, hdig, c->s_main));
@@ -1147,7 +1343,7 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         for (uint32_t i = 0; i < ncs && (uint64_t)i * piece < dw; ++i) {
             const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, dw - lo);
             if ((e = hipStreamWaitEvent(c->s_copy[i], ev[0], 0)) != hipSuccess) return fail(e);
-            if ((e = copy_out(lo, c->staging.as<uint8_t>() + lo, len, c->s_copy[i])) != hipSuccess) return fail(e);
+            if ((e = copy_out(lo, B.staging->as<uint8_t>() + lo, len, c->s_copy[i])) != hipSuccess) return fail(e);
         }
         pos = dw;
     } else {
@@ -1156,8 +1352,10 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         // a copy that has already been issued.
         const bool ahead = nslots >= 2;
         if (W && codec) e = launch_codec(&pos);
-        else if (W) e = two_pass ? launch_two_pass() : launch_window(0, 0);
-        for (uint64_t w = 0; w < W && e == hipSuccess && !codec; ++w) {
+        else if (W && two_pass) e = launch_delta(&pos);
+        else if (W) e = launch_window(0, 0);
+        for (uint64_t w = 0; w < W && e == hipSuccess && !codec && !two_pass; ++w) {
+            const uint64_t q = w % kRing;
             if (w > 0 && !ahead) {
                 e = launch_window(w, pos);
                 if (e != hipSuccess) break;
@@ -1166,9 +1364,15 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
                 e = launch_window(w + 1, 0);
                 if (e != hipSuccess) break;
             }
-            e = hipEventSynchronize(ev[w]);
+            e = hipEventSynchronize(ev[q]);
             if (e != hipSuccess) break;
-            const uint64_t dw = hw[w];
+            if (timing) {
+                // the window's timing pair is complete: its ring entry can be reused
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, c->tevents[2 * q], c->tevents[2 * q + 1]) == hipSuccess)
+                    kern_ns += (uint64_t)((double)ms * 1e6);
+            }
+            const uint64_t dw = hw[q];
             if (stage_all) {
                 // payload stays in staging (its capacity is the whole image)
                 if (pos + dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
@@ -1176,20 +1380,20 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
                 continue;
             }
             if (dw > slot || pos + dw > upper) { e = hipErrorIllegalState; break; }
-            if (!alloc_image(dw)) { e = hipErrorOutOfMemory; break; }
+            if (!alloc_image(pos + dw)) { e = hipErrorOutOfMemory; break; }
             const int s = (int)(w % nslots);
             hipStream_t cs = c->s_copy[w % ncs];
             if (!t_link0) t_link0 = now_ns();
             // device-side dependency on the window's kernel: the host wait above
             // gives the payload length, but only a stream dependency orders the
             // copy engine's reads after the kernel's stores
-            e = hipStreamWaitEvent(cs, ev[w], 0);
+            e = hipStreamWaitEvent(cs, ev[q], 0);
             if (e != hipSuccess) break;
             if (dw) {
-                e = copy_out(pos, c->staging.as<uint8_t>() + (uint64_t)s * slot, dw, cs);
+                e = copy_out(pos, B.staging->as<uint8_t>() + (uint64_t)s * slot, dw, cs);
                 if (e != hipSuccess) break;
             }
-            e = hipEventRecord(ev[W + s], cs);
+            e = hipEventRecord(ev[kRing + s], cs);
             pos += dw;
         }
         if (e == hipSuccess && stage_all) {
@@ -1200,37 +1404,39 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             const uint64_t piece = (std::max<uint64_t>(ceil_div(pos, ncs), 1ull << 20) + 4095) & ~4095ull;
             for (uint32_t i = 0; e == hipSuccess && i < ncs && (uint64_t)i * piece < pos; ++i) {
                 const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, pos - lo);
-                e = hipStreamWaitEvent(c->s_copy[i], ev[W - 1], 0);
-                if (e == hipSuccess) e = copy_out(lo, c->staging.as<uint8_t>() + lo, len, c->s_copy[i]);
+                e = hipStreamWaitEvent(c->s_copy[i], ev[(W - 1) % kRing], 0);
+                if (e == hipSuccess) e = copy_out(lo, B.staging->as<uint8_t>() + lo, len, c->s_copy[i]);
             }
         }
         if (e != hipSuccess) return fail(e);
 
         // per-allocation CRCs -> AllocRec[] (in the device arc buffer)
+        if (timing && (e = hipEventRecord(c->sev[2], c->s_main)) != hipSuccess) return fail(e);
         CombineJob cj;
         memset(&cj, 0, sizeof(cj));
-        cj.allocs = c->descs.as<AllocDesc>();
+        cj.allocs = B.descs->as<AllocDesc>();
         cj.n_allocs = n;
         cj.C = C;
         cj.crc = crc_dev;
         cj.ec = ec;
-        cj.recs = c->arc.as<uint8_t>();
+        cj.recs = B.arc->as<uint8_t>();
         cj.mode = kCombineWrite;
         if ((e = launch_combine(cj, c->s_main)) != hipSuccess) return fail(e);
         // table digests
-        int rc = device_table_digests(c, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, hdig, res);
+        int rc = device_table_digests(c, B.arc->as<uint8_t>(), len_a, kind_dev, len_b, hdig, res, B.dig, dig_ec);
         if (rc) return fail(hipErrorUnknown);
     }
     const uint64_t D = pos;
     if (!alloc_image(D)) return fail(hipErrorOutOfMemory);   // a table without chunks
     // tables into the image
-    if ((e = hipMemcpyAsync(himg + kHeader, c->arc.p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
+    if ((e = hipMemcpyAsync(himg + kHeader, B.arc->p, len_a, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess)
         return fail(e);
     if (codec) memcpy(himg + kHeader + len_a, rlen_h, rl_bytes);   // little-endian host
     if ((e = hipMemcpyAsync(himg + kHeader + len_a + rl_bytes, kind_dev, len_b, hipMemcpyDeviceToHost, c->s_main)) !=
         hipSuccess)
         return fail(e);
     if ((e = hipMemcpyAsync(hdig + 2, err, 4, hipMemcpyDeviceToHost, c->s_main)) != hipSuccess) return fail(e);
+    if (timing && !use_graph && (e = hipEventRecord(c->sev[3], c->s_main)) != hipSuccess) return fail(e);
     if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
     for (uint32_t i = 0; i < ncs; ++i)
         if ((e = hipStreamSynchronize(c->s_copy[i])) != hipSuccess) return fail(e);
@@ -1257,8 +1463,9 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
     put32(h + 60, host_crc32c(h, 60));
     im->n = kHeader + tl + D;
 
-    // keep this image's digest table resident for later delta dumps
-    digest_insert(c, im->uid, crc_dev, nc, c->s_main);
+    // keep this image's digest table resident for later delta dumps (not
+    // for the caller's buffer of a no-allocation dump: that would allocate)
+    if (!na) digest_insert(c, im->uid, crc_dev, nc, c->s_main);
     if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return fail(e);
     if (res) {
         res->windows = (uint32_t)W;
@@ -1267,8 +1474,34 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
         res->n_chunks = nc;
         res->link_bytes = D + tl + kHeader;
         res->ns_link = t_link0 ? t_link1 - t_link0 : 0;
-        res->ns_kernel = timing ? timed_ns(c, codec && W ? codec_pairs : W) : 0;
+        res->ns_kernel = !timing ? 0 : (codec && W) ? timed_ns(c, codec_pairs) : use_graph ? timed_ns(c, 1) : kern_ns;
+        if (timing && two_pass)
+            for (uint64_t i = 0; i < delta_pieces; ++i) res->ns_kernel += span_ns(c->tevents[4 * i], c->tevents[4 * i + 3]);
         res->ns_total = now_ns() - t_start;
+        // per-stage report (see ckpt_result.ns_stage)
+        if (timing) {
+            if (!use_graph) res->ns_stage[0] = span_ns(c->sev[0], c->sev[1]);
+            if (two_pass) {
+                for (uint64_t i = 0; i < delta_pieces; ++i) {
+                    res->ns_stage[1] += span_ns(c->tevents[4 * i], c->tevents[4 * i + 1]);
+                    res->ns_stage[2] += span_ns(c->tevents[4 * i + 1], c->tevents[4 * i + 2]);
+                    res->ns_stage[3] += span_ns(c->tevents[4 * i + 2], c->tevents[4 * i + 3]);
+                }
+            } else if (codec && W) {
+                uint64_t main_ns = 0, aux_ns = 0;   // classify + size pass; gather + encode
+                for (uint64_t i = 0; i < codec_pairs / 2; ++i) {
+                    main_ns += span_ns(c->tevents[2 * i], c->tevents[2 * i + 1]);
+                    aux_ns += span_ns(c->tevents[2 * (codec_pairs / 2 + i)], c->tevents[2 * (codec_pairs / 2 + i) + 1]);
+                }
+                res->ns_stage[1] = main_ns;
+                res->ns_stage[3] = aux_ns;
+            } else {
+                res->ns_stage[1] = res->ns_kernel;
+            }
+            if (!use_graph && W) res->ns_stage[5] = span_ns(c->sev[2], c->sev[3]);
+        }
+        res->ns_stage[4] = res->ns_link;
+        res->ns_stage[7] = res->ns_total;
         const uint8_t* kinds = himg + kHeader + len_a + rl_bytes;
         for (uint64_t i = 0; i < nc; ++i) {
             if (kinds[i] == kZero) ++res->n_zero;
@@ -1277,7 +1510,8 @@ int mk::dump_impl(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* 
             else ++res->n_unchanged;
         }
     }
-    *out = im;
+    if (na) *na->len = im->n;
+    if (out) *out = na ? nullptr : im;
     return CKPT_OK;
 }
 
@@ -1291,16 +1525,33 @@ extern "C" int ckpt_dump(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_
     return dump_impl(c, table, prev, out, o, stream, res, nullptr);
 }
 
+int mk::dump_fixed(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, const ckpt_opts* o,
+                   void* stream, ckpt_result* res, const NaCall& na) {
+    const int rc = dump_run(c, table, prev, nullptr, o, stream, res, nullptr, &na);
+    if (rc != CKPT_OK) drain(c);
+    return rc;
+}
+
 // ------------------------------------------------------------ restore
 // Restore. With `some` false the table is the image's whole table, in order
 // (EMISMATCH otherwise). With `some` true it lists a subset of the image's
 // allocations by id, in any order (on-demand restore): only their chunks
 // are moved, verified and written; the others' memory is never touched.
+static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                       void* stream, ckpt_result* res, bool some, LoadGate* gate);
+
 int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
-                 void* stream, ckpt_result* res, bool some, LoadGate* gate) {
+                     void* stream, ckpt_result* res, bool some, LoadGate* gate) {
+    const int rc = restore_run(c, img, table, o, stream, res, some, gate);
+    if (rc != CKPT_OK) drain(c);
+    return rc;
+}
+
+static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
+                       void* stream, ckpt_result* res, bool some, LoadGate* gate) {
     const uint64_t t_start = now_ns();
     // CKPT_OPT_CODEC is accepted and has no effect: the image says how it is stored
-    if (o && (o->reserved ||
+    if (o && (o->strict_verify > 1 ||
               (o->flags & ~(CKPT_OPT_PER_ALLOC | CKPT_OPT_GRAPH | CKPT_OPT_NO_TIMING | CKPT_OPT_CODEC))))
         return CKPT_EINVAL;
     const uint32_t n = table->n;
@@ -1379,8 +1630,13 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     // uploads on one copy stream: the long launch runs while the short tail
     // is uploaded (the tail's upload ends before the long launch does, so the
     // device never waits idle between the two).
-    const bool tail = !per_alloc && !codec && !gate && !(o && o->window_bytes) && wins.size() == 1 && nc >= 128 &&
-                      nc * C >= kTailMinBytes;
+    // Batched form: a full plain image held by one window restores as one
+    // captured graph per table shape (restore_graph below); a delta, a codec
+    // image, an on-demand or file-gated restore takes the launches below.
+    const bool use_graph = o && (o->flags & CKPT_OPT_GRAPH) && !some && !gate && !codec && !per_alloc &&
+                           !(v.flags & kFlagDelta) && nc > 0 && wins.size() == 1;
+    const bool tail = !use_graph && !per_alloc && !codec && !gate && !(o && o->window_bytes) && wins.size() == 1 &&
+                      nc >= 128 && nc * C >= kTailMinBytes;
     const uint64_t g_tail = tail ? nc - nc / 64 : 0;
     if (tail) wins = {Window{0, g_tail}, Window{g_tail, nc}};
     const uint64_t W = wins.size();
@@ -1396,10 +1652,10 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     if (codec) HIPCHK(c->rlen.ensure(4 * std::max<uint64_t>(nc, 1)));
     HIPCHK(c->wb.ensure(8 * (W + 2)));
     HIPCHK(c->staging.ensure((uint64_t)nslots * slot));
-    HIPCHK(c->status.ensure(8 * (ceil_div(nc, 256) + 64)));
-    // ctl: ticket[1] | counts[4] u64 | bad u64 | bad2 u64 | err | window tickets[W]
+    HIPCHK(c->status.ensure(8 * (ceil_div(nc, 256) + 64), c->s_main));
+    // ctl: ticket[1] | counts[4] u64 | bad u64 | bad2 u64 | err (+pad) | bad3 u64 | window tickets[W + 2]
     const uint64_t ctl_cnt = 64, ctl_bad = ctl_cnt + 32, ctl_bad2 = ctl_bad + 8, ctl_err = ctl_bad2 + 8,
-                   ctl_wtk = ctl_err + 8;
+                   ctl_bad3 = ctl_err + 8, ctl_wtk = ctl_bad3 + 8;
     HIPCHK(c->ctl.ensure(ctl_wtk + 4 * (W + 2) + 64));
     HIPCHK(ensure_hsmall(c, 8 * (W + 2) + 128));
     HIPCHK(ensure_events(c, std::max<size_t>(2 * W + (size_t)nslots + 2, ncs)));
@@ -1412,10 +1668,217 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctl + ctl_cnt);
     unsigned long long* bad = reinterpret_cast<unsigned long long*>(ctl + ctl_bad);
     unsigned long long* bad2 = reinterpret_cast<unsigned long long*>(ctl + ctl_bad2);
+    unsigned long long* bad3 = reinterpret_cast<unsigned long long*>(ctl + ctl_bad3);   // strict re-read
     uint32_t* err = reinterpret_cast<uint32_t*>(ctl + ctl_err);
     uint32_t* wtk = reinterpret_cast<uint32_t*>(ctl + ctl_wtk);
     uint32_t* crc_dev = reinterpret_cast<uint32_t*>(c->arc.as<uint8_t>() + 32ull * v.n_allocs);
     uint8_t* kind_dev = c->kinds.as<uint8_t>();
+
+    if (use_graph) {
+        // ---- batched form: tables and payload uploaded, then one captured
+        // graph validates (tables digest, kinds, payload total) on the device,
+        // and only if the image passes scatters, verifies and checks every
+        // allocation; a rejected image leaves the allocations untouched.
+        // The table is matched on the host first (its sizes bound every write).
+        bool match = v.n_allocs == n;
+        for (uint32_t a = 0; a < n && match; ++a)
+            match = table->v[a].id == d[a].id && table->v[a].size == d[a].size;
+        if (!match) {
+            // the oracle's order: a corrupt image is ECORRUPT before it is a mismatch
+            ImageView full;
+            return parse_image(img->p, img->n, &full, true) ? CKPT_ECORRUPT : CKPT_EMISMATCH;
+        }
+        const bool strict = o && o->strict_verify;
+        const uint64_t ctl_prm = round16(ctl_wtk + 4 * (W + 2)), ctl_gate = ctl_prm + 16;
+        uint64_t* prm = reinterpret_cast<uint64_t*>(ctl + ctl_prm);
+        uint32_t* gflag = reinterpret_cast<uint32_t*>(ctl + ctl_gate);
+        uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall);
+        uint64_t* hq = reinterpret_cast<uint64_t*>(c->hsmall + 64);    // counts[4], bad, bad2, err, bad3
+        uint64_t* hg = reinterpret_cast<uint64_t*>(c->hsmall + 128);   // payload total, gate
+        uint64_t* hp = reinterpret_cast<uint64_t*>(c->hsmall + 192);   // expected tables digest, D
+        HIPCHK(ensure_hsmall(c, 256));
+        HIPCHK(c->amap.ensure(4 * nc));
+        uint64_t key = 0xcbf29ce484222325ull ^ 0x5245535452ull;   // restore graphs
+        auto mix = [&key](uint64_t x) { key = (key ^ x) * 1099511628211ull; };
+        mix(v.n_allocs); mix(C); mix((uint64_t)T); mix((uint64_t)K); mix(nc); mix(len_a); mix(len_b); mix(strict);
+        for (const AllocDesc& x : d) { mix(x.id); mix(x.ptr); mix(x.size); }
+        const void* ptrs[] = {c->arc.p, c->kinds.p, c->off.p, c->wb.p, c->staging.p, c->ctl.p, c->hsmall, ec,
+                              c->amap.p};
+        for (const void* q : ptrs) mix(reinterpret_cast<uint64_t>(q));
+        GraphEntry* ge = nullptr;
+        for (auto& x : c->graphs)
+            if (x.key == key && x.exec) ge = &x;
+        hipError_t e;
+        if (!ge) {
+            const size_t kMaxGraphs = 4;
+            if (c->graphs.size() >= kMaxGraphs) {
+                auto victim = c->graphs.begin();
+                for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it)
+                    if (it->last_use < victim->last_use) victim = it;
+                if (victim->exec) hipGraphExecDestroy(victim->exec);
+                victim->descs.release();
+                victim->dig.release();
+                victim->status.release();
+                c->graphs.erase(victim);
+            }
+            c->graphs.emplace_back();
+            ge = &c->graphs.back();
+            ge->key = key;
+            auto drop = [&](hipError_t err_) {
+                ge->exec = nullptr;
+                if (res) res->hip_error = (int32_t)err_;
+                return err_ == hipErrorOutOfMemory ? CKPT_ENOMEM : CKPT_EHIP;
+            };
+            if ((e = ge->descs.ensure(sizeof(AllocDesc) * d.size())) != hipSuccess) return drop(e);
+            if ((e = ge->status.ensure(8 * (ceil_div(nc, 256) + 64))) != hipSuccess) return drop(e);
+            if ((e = hipMemcpy(ge->descs.p, d.data(), sizeof(AllocDesc) * d.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+                return drop(e);
+            DigestPlan dp;
+            if ((e = digest_prepare(c, &ge->dig, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, &dp, c->s_main)) !=
+                hipSuccess)
+                return drop(e);
+            int grid, vgrid;
+            if ((e = grid_for(c, T, K, kModeRestore, nc, &grid)) != hipSuccess) return drop(e);
+            if ((e = grid_for(c, T, K, kModeVerify, nc, &vgrid)) != hipSuccess) return drop(e);
+            // the digest plan's small tables are prepared; nothing of it is captured
+            if ((e = hipStreamSynchronize(c->s_main)) != hipSuccess) return drop(e);
+            hipGraph_t graph = nullptr;
+            if ((e = hipStreamBeginCapture(c->s_main, hipStreamCaptureModeThreadLocal)) != hipSuccess) return drop(e);
+            hipError_t ce = hipSuccess;
+            auto step = [&ce](hipError_t r) { if (ce == hipSuccess) ce = r; };
+            // every replay clears its control words and look-back words with
+            // fill kernels (no memset nodes); one epoch serves all replays
+            step(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, ctl_bad / 4, c->s_main));
+            step(launch_fill64(reinterpret_cast<uint64_t*>(bad), ~0ull, 2, c->s_main));
+            step(launch_fill32(err, 0, 2, c->s_main));
+            step(launch_fill64(reinterpret_cast<uint64_t*>(bad3), ~0ull, 1, c->s_main));
+            step(launch_fill32(wtk, 0, W + 2, c->s_main));
+            step(launch_fill32(gflag, 0, 1, c->s_main));
+            step(launch_fill64(ge->status.as<uint64_t>(), 0, ceil_div(nc, 256) + 64, c->s_main));
+            step(launch_chunk_map(ge->descs.as<AllocDesc>(), (uint32_t)d.size(), C, c->amap.as<uint32_t>(), c->s_main));
+            step(digest_enqueue(c, dp, hdig, c->s_main));
+            OffJob oj;
+            memset(&oj, 0, sizeof(oj));
+            oj.allocs = ge->descs.as<AllocDesc>();
+            oj.n_allocs = v.n_allocs;
+            oj.C = C;
+            oj.amap = c->amap.as<uint32_t>();
+            oj.n_chunks = nc;
+            oj.kind = kind_dev;
+            oj.off = c->off.as<uint64_t>();
+            oj.per_window = nc + 1;
+            oj.wb = c->wb.as<uint64_t>();
+            oj.n_windows = 1;
+            oj.status = ge->status.as<uint64_t>();
+            oj.ticket = ticket;
+            oj.counts = counts;
+            oj.err = err;
+            oj.epoch = 1;
+            step(launch_offsets(oj, (int)std::min<uint64_t>(ceil_div(nc, 256), 8ull * c->num_cu), c->s_main));
+            GateJob gj;
+            memset(&gj, 0, sizeof(gj));
+            gj.dig = reinterpret_cast<const uint32_t*>(dp.base + dp.off_out);
+            gj.xlen = xpow8(len_b);
+            gj.counts = counts;
+            gj.total = c->wb.as<uint64_t>() + 1;
+            gj.n_chunks = nc;
+            gj.expect = prm;
+            gj.gate = gflag;
+            step(launch_gate(gj, c->s_main));
+            ChunkJob j;
+            memset(&j, 0, sizeof(j));
+            j.allocs = ge->descs.as<AllocDesc>();
+            j.n_allocs = (uint32_t)v.n_allocs;
+            j.C = C;
+            j.amap = c->amap.as<uint32_t>();
+            j.g0 = 0;
+            j.g1 = nc;
+            j.ec = ec;
+            j.kind_in = kind_dev;
+            j.ref_crc = crc_dev;
+            j.slot = c->staging.as<uint8_t>();
+            j.off = c->off.as<uint64_t>();
+            j.slot_base = 0;
+            j.bad = bad;
+            j.err = err;
+            j.gate = gflag;
+            step(launch_chunks(T, K, kModeRestore, one_job(j, wtk), grid, c->s_main));
+            if (strict) {
+                j.bad = bad3;
+                j.flags = kJobVerifyAll;
+                step(launch_chunks(T, K, kModeVerify, one_job(j, wtk + 1), vgrid, c->s_main));
+            }
+            CombineJob cj;
+            memset(&cj, 0, sizeof(cj));
+            cj.allocs = ge->descs.as<AllocDesc>();
+            cj.n_allocs = (uint32_t)v.n_allocs;
+            cj.C = C;
+            cj.crc = crc_dev;
+            cj.ec = ec;
+            cj.recs = c->arc.as<uint8_t>();
+            cj.bad = bad2;
+            cj.mode = kCombineCheck;
+            step(launch_combine(cj, c->s_main));
+            step(hipMemcpyAsync(hq, counts, 64, hipMemcpyDeviceToHost, c->s_main));   // counts, bad, bad2, err, bad3
+            step(hipMemcpyAsync(hg, c->wb.as<uint64_t>() + 1, 8, hipMemcpyDeviceToHost, c->s_main));
+            step(hipMemcpyAsync(hg + 1, gflag, 4, hipMemcpyDeviceToHost, c->s_main));
+            hipError_t ee = hipStreamEndCapture(c->s_main, &graph);
+            if (ce == hipSuccess) ce = ee;
+            if (ce == hipSuccess) ce = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
+            if (graph) hipGraphDestroy(graph);
+            if (ce != hipSuccess) return drop(ce);
+        }
+        ge->last_use = ++c->use_clock;
+        // tables and payload up; what the graph checks the image against
+        hg[1] = 0;
+        hp[0] = v.tables_crc;
+        hp[1] = v.D;
+        const uint64_t t_link0 = now_ns();
+        HIPCHK(hipMemcpyAsync(c->arc.p, v.recs, len_a, hipMemcpyHostToDevice, c->s_main));
+        HIPCHK(hipMemcpyAsync(kind_dev, v.kinds, len_b, hipMemcpyHostToDevice, c->s_main));
+        HIPCHK(hipMemcpyAsync(prm, hp, 16, hipMemcpyHostToDevice, c->s_main));
+        const uint64_t piece = (std::max<uint64_t>(ceil_div(v.D, ncs), 1ull << 20) + 4095) & ~4095ull;
+        for (uint32_t i = 0; i < ncs && (uint64_t)i * piece < v.D; ++i) {
+            const uint64_t lo = (uint64_t)i * piece, len = std::min(piece, v.D - lo);
+            HIPCHK(hipMemcpyAsync(c->staging.as<uint8_t>() + lo, v.payload + lo, len, hipMemcpyHostToDevice,
+                                  c->s_copy[i]));
+            HIPCHK(hipEventRecord(c->events[i], c->s_copy[i]));
+            HIPCHK(hipStreamWaitEvent(c->s_main, c->events[i], 0));
+        }
+        if (timing) HIPCHK(hipEventRecord(c->tevents[0], c->s_main));
+        HIPCHK(hipGraphLaunch(ge->exec, c->s_main));
+        if (timing) HIPCHK(hipEventRecord(c->tevents[1], c->s_main));
+        HIPCHK(hipStreamSynchronize(c->s_main));
+        const uint64_t t_done = now_ns();
+        if (res) {
+            res->windows = 1;
+            res->n_logical = v.N;
+            res->n_payload = v.D;
+            res->n_chunks = nc;
+            res->n_zero = hq[0];
+            res->n_data = hq[1];
+            res->link_bytes = v.D + tl + kHeader;
+            res->ns_link = t_done - t_link0;
+            res->ns_kernel = timing ? timed_ns(c, 1) : 0;
+            res->ns_total = now_ns() - t_start;
+            res->ns_stage[0] = t_link0 - t_start;
+            res->ns_stage[2] = res->ns_link;
+            res->ns_stage[3] = res->ns_kernel;
+            res->ns_stage[7] = res->ns_total;
+        }
+        if (hg[1] != 1) return CKPT_ECORRUPT;   // tables digest, kinds or payload total rejected: nothing written
+        if ((uint32_t)hq[6] != 0) {
+            if (res) res->hip_error = (int32_t)hipErrorLaunchTimeOut;
+            return CKPT_EHIP;
+        }
+        const uint64_t first_bad = std::min<uint64_t>(hq[4], hq[7]);
+        if (first_bad != kNoChunk || hq[5] != kNoChunk) {
+            if (res) res->first_bad_chunk = first_bad != kNoChunk ? first_bad : hq[5];
+            return CKPT_ECORRUPT;
+        }
+        return CKPT_OK;
+    }
 
     // 1) tables up, their digest, payload offsets
     HIPCHK(c->amap.ensure(4 * std::max<uint64_t>(nc, 1)));
@@ -1425,9 +1888,11 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     HIPCHK(hipMemcpyAsync(kind_dev, v.kinds, len_b, hipMemcpyHostToDevice, c->s_main));
     HIPCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, ctl_bad / 4, c->s_main));
     HIPCHK(launch_fill64(reinterpret_cast<uint64_t*>(bad), ~0ull, 2, c->s_main));
-    HIPCHK(launch_fill32(err, 0, 2 + W + 2, c->s_main));
+    HIPCHK(launch_fill32(err, 0, 2, c->s_main));
+    HIPCHK(launch_fill32(wtk, 0, W + 2, c->s_main));
     uint32_t* hdig = reinterpret_cast<uint32_t*>(c->hsmall);
-    uint64_t* hq = reinterpret_cast<uint64_t*>(c->hsmall + 64);   // counts[4], bad, bad2, err
+    HIPCHK(launch_fill64(reinterpret_cast<uint64_t*>(bad3), ~0ull, 1, c->s_main));
+    uint64_t* hq = reinterpret_cast<uint64_t*>(c->hsmall + 64);   // counts[4], bad, bad2, err, bad3
     uint64_t* hwb = reinterpret_cast<uint64_t*>(c->hsmall + 128);
     rc = device_table_digests(c, c->arc.as<uint8_t>(), len_a, kind_dev, len_b, hdig, res);
     if (rc) return rc;
@@ -1457,9 +1922,8 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         }
     }
     if (nc && !codec) {
-        bool wrapped;
-        const uint32_t ep = next_epoch(c, &wrapped);
-        if (wrapped) HIPCHK(launch_fill64(c->status.as<uint64_t>(), 0, c->status.cap / 8, c->s_main));
+        uint32_t ep;
+        HIPCHK(c->status.next(c->s_main, &ep));
         OffJob oj;
         memset(&oj, 0, sizeof(oj));
         oj.allocs = c->descs.as<AllocDesc>();
@@ -1474,7 +1938,7 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         oj.per_window = per_alloc ? nc + 1 : tail ? g_tail : std::max<uint64_t>(1, slot / C);
         oj.wb = c->wb.as<uint64_t>();
         oj.n_windows = per_alloc ? 1 : W;
-        oj.status = c->status.as<uint64_t>();
+        oj.status = c->status.words();
         oj.ticket = ticket;
         oj.counts = counts;
         oj.err = err;
@@ -1545,8 +2009,11 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
             if (table->v[a].id != d[a].id || table->v[a].size != d[a].size) return CKPT_EMISMATCH;
     }
 
-    // 2) a delta needs its base in place
-    if (nu) {
+    // Verify-mode pass over the chunks being restored (all of them, or the
+    // listed allocations' windows, up to kMaxJobs windows per launch): the
+    // UNCHANGED chunks' base check, or with kJobVerifyAll every chunk (the
+    // strict re-read). The lowest failing chunk goes to *badp.
+    auto verify_pass = [&](uint32_t flags, unsigned long long* badp) -> hipError_t {
         ChunkJob j;
         memset(&j, 0, sizeof(j));
         j.allocs = c->descs.as<AllocDesc>();
@@ -1558,33 +2025,39 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         j.ec = ec;
         j.kind_in = kind_dev;
         j.ref_crc = crc_dev;
-        j.bad = bad;
+        j.bad = badp;
         j.err = err;
+        j.flags = flags;
         int grid;
+        hipError_t e;
         if (!some) {
-            HIPCHK(grid_for(c, T, K, kModeVerify, nc, &grid));
-            HIPCHK(launch_chunks(T, K, kModeVerify, one_job(j, wtk + W), grid, c->s_main));
-        } else {
-            // only the chunks being restored, up to kMaxJobs windows per launch
-            for (uint64_t w0 = 0; w0 < W; w0 += kMaxJobs) {
-                JobList jl;
-                memset(&jl, 0, sizeof(jl));
-                uint64_t tot = 0;
-                for (uint64_t w = w0; w < std::min<uint64_t>(W, w0 + kMaxJobs); ++w) {
-                    jl.job[jl.n_jobs] = j;
-                    jl.job[jl.n_jobs].g0 = wins[w].g0;
-                    jl.job[jl.n_jobs].g1 = wins[w].g1;
-                    jl.prefix[jl.n_jobs] = tot;
-                    tot += wins[w].g1 - wins[w].g0;
-                    jl.n_jobs++;
-                }
-                jl.prefix[jl.n_jobs] = tot;
-                jl.ticket = wtk + W;
-                HIPCHK(launch_fill32(wtk + W, 0, 1, c->s_main));
-                HIPCHK(grid_for(c, T, K, kModeVerify, tot, &grid));
-                HIPCHK(launch_chunks(T, K, kModeVerify, jl, grid, c->s_main));
-            }
+            if ((e = grid_for(c, T, K, kModeVerify, nc, &grid)) != hipSuccess) return e;
+            return launch_chunks(T, K, kModeVerify, one_job(j, wtk + W), grid, c->s_main);
         }
+        for (uint64_t w0 = 0; w0 < W; w0 += kMaxJobs) {
+            JobList jl;
+            memset(&jl, 0, sizeof(jl));
+            uint64_t tot = 0;
+            for (uint64_t w = w0; w < std::min<uint64_t>(W, w0 + kMaxJobs); ++w) {
+                jl.job[jl.n_jobs] = j;
+                jl.job[jl.n_jobs].g0 = wins[w].g0;
+                jl.job[jl.n_jobs].g1 = wins[w].g1;
+                jl.prefix[jl.n_jobs] = tot;
+                tot += wins[w].g1 - wins[w].g0;
+                jl.n_jobs++;
+            }
+            jl.prefix[jl.n_jobs] = tot;
+            jl.ticket = wtk + W;
+            if ((e = grid_for(c, T, K, kModeVerify, tot, &grid)) != hipSuccess) return e;
+            if ((e = launch_chunks(T, K, kModeVerify, jl, grid, c->s_main)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const uint64_t t_valid = now_ns();
+
+    // 2) a delta needs its base in place
+    if (nu) {
+        HIPCHK(verify_pass(0, bad));
         HIPCHK(hipMemcpyAsync(hq + 4, bad, 8, hipMemcpyDeviceToHost, c->s_main));
         HIPCHK(hipStreamSynchronize(c->s_main));
         if (hq[4] != kNoChunk) {
@@ -1592,6 +2065,7 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
             return CKPT_EBASE;
         }
     }
+    const uint64_t t_based = now_ns();
 
     // 3) windows: payload slice up, scatter + verify
     std::vector<hipEvent_t>& ev = c->events;   // [0,W): copied; [W, W+nslots): slot free
@@ -1703,7 +2177,17 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w + 1], c->s_main));
         HIPCHK(hipEventRecord(ev[W + s], c->s_main));
     }
+    // strict mode: every restored chunk re-read from HBM once all writes are
+    // done, its CRC-32C checked again (the fused check ran on the data in
+    // registers as it was written)
+    const bool strict = o && o->strict_verify;
+    if (strict) {
+        if (timing) HIPCHK(hipEventRecord(c->sev[0], c->s_main));
+        HIPCHK(verify_pass(kJobVerifyAll, bad3));
+        if (timing) HIPCHK(hipEventRecord(c->sev[1], c->s_main));
+    }
     // 4) whole-allocation CRCs
+    if (timing) HIPCHK(hipEventRecord(c->sev[2], c->s_main));
     CombineJob cj;
     memset(&cj, 0, sizeof(cj));
     cj.allocs = c->descs.as<AllocDesc>();
@@ -1715,7 +2199,8 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
     cj.bad = bad2;
     cj.mode = kCombineCheck;
     HIPCHK(launch_combine(cj, c->s_main));
-    HIPCHK(hipMemcpyAsync(hq + 4, bad, 24, hipMemcpyDeviceToHost, c->s_main));
+    if (timing) HIPCHK(hipEventRecord(c->sev[3], c->s_main));
+    HIPCHK(hipMemcpyAsync(hq + 4, bad, 32, hipMemcpyDeviceToHost, c->s_main));   // bad, bad2, err, bad3
     HIPCHK(hipStreamSynchronize(c->s_main));
     for (uint32_t i = 0; i < ncs; ++i) HIPCHK(hipStreamSynchronize(c->s_copy[i]));
     const uint64_t t_link1 = now_ns();
@@ -1740,9 +2225,19 @@ int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table*
         res->ns_link = t_link1 - t_link0;
         res->ns_kernel = timing ? timed_ns(c, merged ? ceil_div(W, (uint64_t)kMaxJobs) : W) : 0;
         res->ns_total = now_ns() - t_start;
+        res->ns_stage[0] = t_valid - t_start;
+        res->ns_stage[1] = nu ? t_based - t_valid : 0;
+        res->ns_stage[2] = res->ns_link;
+        res->ns_stage[3] = res->ns_kernel;
+        if (timing && strict) res->ns_stage[4] = span_ns(c->sev[0], c->sev[1]);
+        if (timing) res->ns_stage[5] = span_ns(c->sev[2], c->sev[3]);
+        res->ns_stage[7] = res->ns_total;
     }
-    if (hq[4] != kNoChunk) {
-        if (res) res->first_bad_chunk = hq[4];
+    // the lowest failing chunk of the fused and the strict checks, then the
+    // per-allocation check
+    const uint64_t first_bad = std::min<uint64_t>(hq[4], hq[7]);
+    if (first_bad != kNoChunk) {
+        if (res) res->first_bad_chunk = first_bad;
         return CKPT_ECORRUPT;
     }
     if (hq[5] != kNoChunk) {

@@ -37,7 +37,8 @@ namespace {
 constexpr uint64_t kDefaultSlot = 256ull << 20;
 
 struct Lane {
-    DevBuf descs, arc, kinds, status, ctl, off, wb, staging, dig, prevcrc, amap;
+    DevBuf descs, arc, kinds, ctl, off, wb, staging, dig, prevcrc, amap;
+    StatusBuf status;
     uint8_t* hs = nullptr;   // pinned: per-window payload lengths / offsets, digests, flags
     uint64_t hs_cap = 0;
     std::vector<hipEvent_t> ev;   // per window: kernel done (dump) or copy done (restore)
@@ -66,8 +67,9 @@ struct Lane {
         return hipSuccess;
     }
     void release() {
-        DevBuf* b[] = {&descs, &arc, &kinds, &status, &ctl, &off, &wb, &staging, &dig, &prevcrc, &amap};
+        DevBuf* b[] = {&descs, &arc, &kinds, &ctl, &off, &wb, &staging, &dig, &prevcrc, &amap};
         for (DevBuf* x : b) x->release();
+        status.release();
         for (hipEvent_t e : ev) hipEventDestroy(e);
         for (hipEvent_t e : slot_ev) if (e) hipEventDestroy(e);
         if (fin) hipEventDestroy(fin);
@@ -93,6 +95,7 @@ struct Req {
     uint64_t nc = 0, tl = 0, upper = 0, per = 0, W = 0, N = 0;
     std::vector<AllocDesc> d;
     const uint32_t* prev_dev = nullptr;
+    uint64_t prev_pinned = 0;  // uid of the resident digest table pinned for this request, or 0
     uint32_t prev_digest = 0;
     ImageView v;               // restore: the image
     // progress
@@ -130,9 +133,14 @@ struct ckpt_server {
 
 namespace {
 
+// Called by the scheduler thread with the context's lock held.
 void finish(ckpt_server* s, Req* r, int rc) {
     r->rc = rc;
     r->t_done = now_ns();
+    if (r->prev_pinned) {
+        digest_unpin(s->ctx, r->prev_pinned);   // no launch of the request reads it any more
+        r->prev_pinned = 0;
+    }
     if (rc != CKPT_OK && r->out) {
         ckpt_image_free(r->out);
         r->out = nullptr;
@@ -184,10 +192,10 @@ void admit_dump(ckpt_server* s, Req* r) {
     ImageView pv;
     std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> pm;
     if (r->rq.prev) {
-        int rc = parse_image(r->rq.prev->p, r->rq.prev->n, &pv, false);
+        int rc = parse_image(r->rq.prev->p, r->rq.prev->n, &pv, true);   // tables digest included
         if (rc) { finish(s, r, rc); return; }
         if (pv.C != r->C) { finish(s, r, CKPT_EINVAL); return; }
-        r->prev_digest = host_crc32c(pv.recs, 32ull * pv.n_allocs + 4 * pv.n_chunks);
+        r->prev_digest = pv.state_digest;
         for (uint64_t a = 0; a < pv.n_allocs; ++a)
             pm.emplace(get64(pv.recs + 32 * a), std::make_pair(get64(pv.recs + 32 * a + 8), get64(pv.recs + 32 * a + 16)));
     }
@@ -211,7 +219,7 @@ void admit_dump(ckpt_server* s, Req* r) {
     SCHK(L.descs.ensure(sizeof(AllocDesc) * std::max<uint32_t>(r->n, 1)));
     SCHK(L.arc.ensure(r->tl + 16));
     SCHK(L.kinds.ensure(r->tl + 16));
-    SCHK(L.status.ensure(8 * (r->per + 64)));
+    SCHK(L.status.ensure(8 * (r->per + 64), s->s_dump));
     SCHK(L.ctl.ensure(16 * (r->W + 2) + 64));
     SCHK(L.staging.ensure(2 * s->slot));
     SCHK(L.ensure_hs(8 * (r->W + 2) + 64));
@@ -219,7 +227,10 @@ void admit_dump(ckpt_server* s, Req* r) {
     r->out = image_new(kHeader + r->tl + r->upper);
     if (!r->out) { finish(s, r, CKPT_ENOMEM); return; }
     if (r->rq.prev && pv.n_chunks) {
-        r->prev_dev = digest_lookup(c, r->rq.prev->uid, pv.n_chunks);
+        // pinned: later windows of this request read it while other requests
+        // complete and insert their own tables
+        r->prev_dev = digest_lookup(c, r->rq.prev->uid, pv.n_chunks, true);
+        if (r->prev_dev) r->prev_pinned = r->rq.prev->uid;
         if (!r->prev_dev) {
             SCHK(L.prevcrc.ensure(4 * pv.n_chunks));
             SCHK(hipMemcpyAsync(L.prevcrc.p, pv.crcs, 4 * pv.n_chunks, hipMemcpyHostToDevice, s->s_dump));
@@ -265,7 +276,7 @@ void admit_restore(ckpt_server* s, Req* r) {
     SCHK(L.kinds.ensure(v.tl + 16));
     SCHK(L.off.ensure(8 * std::max<uint64_t>(v.n_chunks, 1)));
     SCHK(L.wb.ensure(8 * (r->W + 2)));
-    SCHK(L.status.ensure(8 * (ceil_div(v.n_chunks, 256) + 64)));
+    SCHK(L.status.ensure(8 * (ceil_div(v.n_chunks, 256) + 64), s->s_rest));
     // ctl: [0] offsets ticket | [8] counts[4] | [40] bad | [48] bad2 | [56] err | [64..] window tickets
     SCHK(L.ctl.ensure(64 + 4 * (r->W + 4)));
     SCHK(L.staging.ensure(2 * s->slot));
@@ -284,9 +295,8 @@ void admit_restore(ckpt_server* s, Req* r) {
     SCHK(digest_prepare(c, &L.dig, L.arc.as<uint8_t>(), len_a, L.kinds.as<uint8_t>(), len_b, &dp, st));
     SCHK(digest_enqueue(c, dp, reinterpret_cast<uint32_t*>(L.hs), st));
     if (v.n_chunks) {
-        bool wrapped;
-        const uint32_t ep = next_epoch(c, &wrapped);
-        if (wrapped) SCHK(launch_fill64(L.status.as<uint64_t>(), 0, L.status.cap / 8, st));
+        uint32_t ep;
+        SCHK(L.status.next(st, &ep));
         OffJob oj;
         memset(&oj, 0, sizeof(oj));
         oj.allocs = L.descs.as<AllocDesc>();
@@ -299,7 +309,7 @@ void admit_restore(ckpt_server* s, Req* r) {
         oj.per_window = r->per;
         oj.wb = L.wb.as<uint64_t>();
         oj.n_windows = r->W;
-        oj.status = L.status.as<uint64_t>();
+        oj.status = L.status.words();
         oj.ticket = reinterpret_cast<uint32_t*>(ctl);
         oj.counts = reinterpret_cast<unsigned long long*>(ctl + 8);
         oj.err = reinterpret_cast<uint32_t*>(ctl + 56);
@@ -408,13 +418,15 @@ void launch_merged(ckpt_server* s, bool dump) {
         uint8_t* slotp = L.staging.as<uint8_t>() + (w % 2) * s->slot;
         j.slot = slotp;
         if (dump) {
-            bool wrapped;
-            j.epoch = next_epoch(c, &wrapped);
-            if (wrapped) launch_fill64(L.status.as<uint64_t>(), 0, L.status.cap / 8, st);
+            if (L.status.next(st, &j.epoch) != hipSuccess) {
+                // a request whose launch cannot be prepared fails alone
+                finish(s, r, CKPT_EHIP);
+                continue;
+            }
             j.crc_out = reinterpret_cast<uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
             j.kind_out = L.kinds.as<uint8_t>();
             j.prev_crc = r->prev_dev;
-            j.status = L.status.as<uint64_t>();
+            j.status = L.status.words();
             j.wtotal = reinterpret_cast<uint64_t*>(L.ctl.as<uint8_t>()) + w;
             j.err = reinterpret_cast<uint32_t*>(L.ctl.as<uint8_t>() + 16 * (r->W + 2));
             // the slot's previous copy must be finished before it is overwritten
@@ -435,6 +447,7 @@ void launch_merged(ckpt_server* s, bool dump) {
         jl.n_jobs++;
         used.push_back(r);
     }
+    if (used.empty()) return;
     jl.prefix[jl.n_jobs] = total;
     uint32_t* tk = next_ticket_slot(s);
     jl.ticket = tk;

@@ -29,6 +29,7 @@ CKPT_EMISMATCH = -5
 CKPT_EBASE = -6
 CKPT_ETIMEOUT = -7
 CKPT_EIO = -8
+CKPT_ELIMIT = -9
 KIND_ZERO, KIND_DATA, KIND_UNCHANGED, KIND_PACKED = 0, 1, 2, 3
 OPT_PER_ALLOC = 1
 OPT_GRAPH = 2
@@ -50,7 +51,7 @@ class ckpt_alloc_table(ctypes.Structure):
 
 class ckpt_opts(ctypes.Structure):
     _fields_ = [("chunk_size", _u32), ("wg_threads", _u32), ("copy_streams", _u32), ("slots", _u32),
-                ("window_bytes", _u64), ("flags", _u32), ("reserved", _u32)]
+                ("window_bytes", _u64), ("flags", _u32), ("strict_verify", _u32)]
 
 
 class ckpt_result(ctypes.Structure):
@@ -58,10 +59,12 @@ class ckpt_result(ctypes.Structure):
                 ("n_logical", _u64), ("n_payload", _u64), ("n_chunks", _u64),
                 ("n_zero", _u64), ("n_data", _u64), ("n_unchanged", _u64),
                 ("link_bytes", _u64), ("ns_total", _u64), ("ns_kernel", _u64), ("ns_link", _u64),
-                ("n_packed", _u64), ("reserved", _u64 * 3)]
+                ("n_packed", _u64), ("reserved", _u64 * 3), ("ns_stage", _u64 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "ns_stage")}
+        d["ns_stage"] = list(self.ns_stage)
+        return d
 
 
 class ckpt_request(ctypes.Structure):
@@ -220,8 +223,8 @@ def _table(entries):
     return tab, (arr, keep)
 
 
-def make_opts(chunk_size=0, wg_threads=0, copy_streams=0, slots=0, window_bytes=0, flags=0):
-    return ckpt_opts(chunk_size, wg_threads, copy_streams, slots, window_bytes, flags, 0)
+def make_opts(chunk_size=0, wg_threads=0, copy_streams=0, slots=0, window_bytes=0, flags=0, strict_verify=0):
+    return ckpt_opts(chunk_size, wg_threads, copy_streams, slots, window_bytes, flags, int(strict_verify))
 
 
 def _stream(stream):

@@ -1,13 +1,16 @@
 """Parity at the benchmark's full sizes and launch configuration.
 
-The oracle cannot re-dump tens of GB quickly, so these tests check what it
-can compute one by one -- CRC-32C and kind of sampled chunks, the payload
-record of sampled chunks, the table digests -- plus properties that hold at
-any size (header fields, payload length, the restored bytes equal to the
-dumped ones, in full). Each test names its workload and seed."""
+Every image dumped here is compared byte for byte with the oracle's image of
+the same device bytes (copied to the host, dumped by the plain-C oracle on
+all host cores): header, allocation records, every crc[] and kind[] entry,
+and the whole payload. Restores are checked by the restored bytes equal to
+the dumped ones, in full. Each test names its workload and seed. The codec
+test compares sampled chunks' records (the oracle's codec at this size takes
+minutes) plus properties that hold at any size."""
 import os
 import struct
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -83,6 +86,50 @@ def _check_image(img, table, samples=1500, seed=0, prev_table=None):
     return D, kinds
 
 
+
+def _first_diff(a, b, step=1 << 28):
+    """Offset of the first differing byte of two equal-length uint8 arrays,
+    compared in slices (no full-size temporaries), or None."""
+    for lo in range(0, a.size, step):
+        x, y = a[lo:lo + step], b[lo:lo + step]
+        if not np.array_equal(x, y):
+            return lo + int(np.nonzero(x != y)[0][0])
+    return None
+
+
+def _same_as_oracle(img, oimg, label):
+    """The GPU image equals the oracle's byte for byte; on a difference the
+    message says which region (header, records, crc[], kind[], payload)
+    holds the first one and how many crc[] / kind[] entries differ."""
+    got = img.view()
+    assert got.size == oimg.size, (label, got.size, oimg.size)
+    at = _first_diff(got, oimg)
+    if at is None:
+        return
+    n = int(np.frombuffer(oimg[20:24].tobytes(), np.uint32)[0])
+    nc = int(np.frombuffer(oimg[24:32].tobytes(), np.uint64)[0])
+    codec = int(np.frombuffer(oimg[12:16].tobytes(), np.uint32)[0]) & 2
+    o_crc = 64 + 32 * n
+    o_kind = o_crc + (8 if codec else 4) * nc
+    crc_g = np.frombuffer(got[o_crc:o_crc + 4 * nc].tobytes(), np.uint32)
+    crc_o = np.frombuffer(oimg[o_crc:o_crc + 4 * nc].tobytes(), np.uint32)
+    kd = int((got[o_kind:o_kind + nc] != oimg[o_kind:o_kind + nc]).sum())
+    region = ("header" if at < 64 else "records" if at < o_crc else "crc" if at < o_crc + 4 * nc
+              else "kind/rlen" if at < o_kind + nc else "tables pad/payload")
+    raise AssertionError("%s: image differs from the oracle's, first at byte %d (%s); %d crc[] and %d kind[] "
+                         "entries differ" % (label, at, region, int((crc_g != crc_o).sum()), kd))
+
+
+def _oracle_dump(host_table, prev=None, label=""):
+    t0 = time.perf_counter()
+    rc, oimg = corc.dump(host_table, C, prev=prev)
+    assert rc == 0
+    print("%s: oracle dump of %.1f GB in %.1f s (%d threads)" % (
+        label, sum(a.size for _, a in host_table) / 1e9, time.perf_counter() - t0, corc.default_threads()),
+        flush=True)
+    return oimg
+
+
 def _mem(tag):
     free, total = torch.cuda.mem_get_info()
     print("%s: device memory free %.1f of %.1f GiB, torch reserved %.1f GiB"
@@ -99,10 +146,11 @@ def _restore_equal(ctx, img, table, opts):
         assert torch.equal(_bytes_of(a), _bytes_of(b))
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_training_state_full_size():
     """decoder-1.3B training state, seed 2, 303 allocations, ~27 GB; the bench's
-    configuration: one staging window, 64 KiB chunks."""
+    configuration: one staging window, 64 KiB chunks. The whole image equals
+    the oracle's."""
     torch.cuda.empty_cache()
     _mem("start")
     table = workloads.training_state("cuda", seed=2)
@@ -113,8 +161,11 @@ def test_training_state_full_size():
         opts = mk.make_opts(chunk_size=C)
         rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
         assert rc == 0 and res.windows == 1
-        D, kinds = _check_image(img, table, seed=2)
+        D, kinds = _check_image(img, table, samples=200, seed=2)
         assert (kinds == DATA).all() and D >= N     # random-valued state: every chunk is DATA
+        oimg = _oracle_dump(workloads.host_copy(table), label="training state")
+        _same_as_oracle(img, oimg, "training state")
+        del oimg
         _restore_equal(ctx, img, table, opts)
         img.free()
     finally:
@@ -173,10 +224,12 @@ def test_training_state_codec_full_size():
         mk.ckpt_ctx_destroy(ctx)
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_hpc_incremental_full_size():
     """HPC image, seed 3, 512 allocations, 40 GB, ~60 % zero chunks; 5 % of the
-    chunks rewritten (seed 33); delta dump, then base restore + delta apply."""
+    chunks rewritten (seed 33); the base image and the delta image (taken
+    against it) each equal the oracle's, the oracle's delta taken against
+    its own base image; then base restore + delta apply in place."""
     torch.cuda.empty_cache()
     _mem("start")
     table, _ = workloads.hpc_state("cuda", seed=3)
@@ -186,12 +239,16 @@ def test_hpc_incremental_full_size():
         opts = mk.make_opts(chunk_size=C)
         rc, base, _ = mk.ckpt_dump(ctx, table, opts=opts)
         assert rc == 0
-        prev = [(i, t.clone()) for i, t in table]
+        obase = _oracle_dump(workloads.host_copy(table), label="HPC base")
+        _same_as_oracle(base, obase, "HPC base")
         workloads.mutate_runs(table, seed=33, chunk=C, frac=0.05, run_mean=16)
+        torch.cuda.synchronize()
         rc, delta, dres = mk.ckpt_dump(ctx, table, prev=base, opts=opts)
         assert rc == 0 and dres.n_unchanged > 0
-        _check_image(delta, table, samples=1500, seed=3, prev_table=prev)
-        del prev
+        odelta = _oracle_dump(workloads.host_copy(table), prev=obase, label="HPC delta")
+        del obase
+        _same_as_oracle(delta, odelta, "HPC delta")
+        del odelta
         # base then delta, in place: equals the new state
         new = [(i, t.clone()) for i, t in table]
         rc, _ = mk.ckpt_restore(ctx, base, table, opts=opts)
@@ -210,35 +267,29 @@ def test_hpc_incremental_full_size():
 
 @pytest.mark.timeout(900)
 def test_fragmented_batched_full_size():
-    """10,000 allocations, seed 4, 60 GB, 256 KiB-aligned zero blocks; graph
-    form (one launch) and per-allocation launches give the same image. Two
-    60 GB pinned images do not fit the host at once, so the two are compared
-    through what fixes an image byte for byte: equal header and tables (so
-    equal kinds and payload layout), and each restoring, verified, to the
-    dumped state (so every payload record holds the chunk's bytes and zero
-    padding)."""
+    """10,000 allocations, seed 4, 60 GB, 256 KiB-aligned zero blocks; the
+    graph form (one launch) and the per-allocation launches each give the
+    oracle's image byte for byte, and each restores the dumped state."""
     torch.cuda.empty_cache()   # 60 GB state + 60 GB staging + 60 GB restore targets
     _mem("start")
     table = workloads.fragmented_state("cuda", seed=4)
     torch.cuda.synchronize()
     _mem("state")
+    oimg = _oracle_dump(workloads.host_copy(table), label="fragmented")
     ctx = mk.ckpt_ctx_create(0, 96 << 30)
     try:
         opts = mk.make_opts(chunk_size=C, flags=mk.OPT_GRAPH)
         rc, img, res = mk.ckpt_dump(ctx, table, opts=opts)
         assert rc == 0, (mk.ckpt_strerror(rc), res.hip_error)
         assert res.windows == 1
-        D, _ = _check_image(img, table, seed=4)
-        v = img.view()
-        n, nc = len(table), res.n_chunks
-        head = v[:64 + ((32 * n + 5 * nc + 15) & ~15)].copy()
+        _same_as_oracle(img, oimg, "fragmented, graph form")
         _restore_equal(ctx, img, table, opts)
         img.free()
         rc, img2, res2 = mk.ckpt_dump(ctx, table, opts=mk.make_opts(chunk_size=C, flags=mk.OPT_PER_ALLOC))
         assert rc == 0, (mk.ckpt_strerror(rc), res2.hip_error)
         assert res2.windows >= len([t for _, t in table if t.numel()])
-        assert img2.view().size == head.size + D
-        assert np.array_equal(img2.view()[:head.size], head)
+        _same_as_oracle(img2, oimg, "fragmented, per-allocation launches")
+        del oimg
         _restore_equal(ctx, img2, table, opts)
         img2.free()
     finally:

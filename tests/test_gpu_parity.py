@@ -16,10 +16,12 @@ sys.path.insert(0, ROOT)
 from oracle import oracle as corc  # noqa: E402
 from paper_2502_16631_amd import mickpt as mk  # noqa: E402
 import workloads  # noqa: E402
+from testlib import crc_collide  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+ZERO, DATA, UNCHANGED = 0, 1, 2
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +100,13 @@ def test_chunk_sizes_ragged_tables(ctx, c):
 @pytest.mark.parametrize("c", [16, 32, 64, 128, 256, 512])
 def test_bruteforce_tiny_chunk_sizes(ctx, c):
     """Sizes around the chunk edges, contents zero / random / single byte,
-    previous image none / same / one byte changed / resized / renamed."""
+    previous image none / same / one byte changed / resized / renamed. The
+    previous image is dumped by both sides and must be identical; each side
+    then takes the delta against its own previous image. Every image is
+    restored: a full one into scratch targets, a delta in place over the
+    previous state (resized / renamed previous states share no allocation
+    with the new table, so such a delta holds no UNCHANGED chunk and is
+    restored into scratch targets)."""
     rng = random.Random(c)
     gen = torch.Generator(device=DEV).manual_seed(c)
     sizes = sorted({0, 1, 15, 16, 17, c - 1, c, c + 1, 2 * c, 2 * c + 5})
@@ -115,7 +123,7 @@ def test_bruteforce_tiny_chunk_sizes(ctx, c):
                 t[0 if kind == "first" else size - 1] = rng.randint(1, 255)
             table.append((10 + a, t))
         pk = rng.choice([None, "same", "byte", "resized", "renamed"])
-        prev_g = prev_o = None
+        prev_g = prev_o = pt = None
         if pk is not None:
             pt = []
             for aid, t in table:
@@ -125,11 +133,67 @@ def test_bruteforce_tiny_chunk_sizes(ctx, c):
                 if pk == "resized":
                     x = torch.cat([x, torch.tensor([7], dtype=torch.uint8, device=DEV)])
                 pt.append((aid + (1000 if pk == "renamed" else 0), x))
-            prev_g, _ = gpu_dump(ctx, pt, chunk_size=c)
-            prev_o = prev_g.tobytes()
-        img, _, _ = check_parity(ctx, table, c, prev_gpu=prev_g, prev_oracle=prev_o)
-        if pk is None:
+            prev_g, prev_o, _ = check_parity(ctx, pt, c)
+        img, oimg, res = check_parity(ctx, table, c, prev_gpu=prev_g, prev_oracle=prev_o)
+        if pk in ("same", "byte"):
+            # base restored, then the delta applied in place
+            targets = [(i, torch.full_like(t, 0x5A) if t.numel() else t.clone()) for i, t in table]
+            rc, r = mk.ckpt_restore(ctx, prev_g, targets)
+            assert rc == 0, (mk.ckpt_strerror(rc), r.first_bad_chunk)
+            rc, r = mk.ckpt_restore(ctx, img, targets)
+            assert rc == 0, (mk.ckpt_strerror(rc), r.first_bad_chunk)
+            torch.cuda.synchronize()
+            for (_, a), (_, b) in zip(table, targets):
+                assert torch.equal(a, b), (trial, pk)
+            # the oracle applies its delta the same way
+            host_t = [(i, x.copy()) for i, x in host(pt)]
+            assert corc.restore(prev_o, host_t)[0] == 0
+            assert corc.restore(oimg, host_t)[0] == 0
+            for (_, a), (_, b) in zip(host(table), host_t):
+                assert np.array_equal(a, b)
+        else:
+            assert res.n_unchanged == 0
             restore_and_compare(ctx, img, table)
+        for x in (img, prev_g):
+            if x is not None:
+                x.free()
+
+
+@pytest.mark.parametrize("c,kw", [(64, {}), (65536, {}), (65536, {"window_bytes": 4 * 65536}),
+                                  (65536, {"flags": mk.OPT_GRAPH}), (16384, {"flags": mk.OPT_PER_ALLOC})])
+def test_forced_crc_collision_is_unchanged(ctx, c, kw):
+    """A chunk rewritten and then patched in 4 bytes so that its CRC-32C equals
+    the base's (solved over GF(2) with the hardware CRC) is UNCHANGED in the
+    delta of both the GPU path and the oracle (digest equality is the
+    unchanged test); every launch form (two-pass delta in one window,
+    single-pass delta over several windows, graph, per-allocation) agrees
+    with the oracle byte for byte."""
+    rng = np.random.default_rng(c + 7)
+    base = [(5, rng.integers(0, 256, 3 * c + 100, dtype=np.uint8)), (6, rng.integers(0, 256, 2 * c, dtype=np.uint8))]
+    new = [(i, a.copy()) for i, a in base]
+    a1 = new[0][1]
+    a1[c + 10] ^= 0xFF                                  # chunk 1 of allocation 5
+    patched = crc_collide(base[0][1][c:2 * c].tobytes(), a1[c:2 * c].tobytes(), 20)
+    a1[c:2 * c] = np.frombuffer(patched, np.uint8)
+    assert not np.array_equal(a1[c:2 * c], base[0][1][c:2 * c])
+    new[1][1][5] ^= 1                                   # an ordinary change in allocation 6
+    dev_base = [(i, torch.from_numpy(a).to(DEV)) for i, a in base]
+    dev_new = [(i, torch.from_numpy(a).to(DEV)) for i, a in new]
+    prev_g, prev_o, _ = check_parity(ctx, dev_base, c, **kw)
+    img, oimg, res = check_parity(ctx, dev_new, c, prev_gpu=prev_g, prev_oracle=prev_o, **kw)
+    kinds = corc_kinds(oimg)
+    assert kinds[1] == UNCHANGED and kinds[4] == DATA and res.n_unchanged == len(kinds) - 1
+    prev_g.free()
+    img.free()
+
+
+def corc_kinds(image):
+    """Kind table of a plain-layout image (header fields at their documented
+    offsets)."""
+    n = int(np.frombuffer(image[20:24].tobytes(), np.uint32)[0])
+    nc = int(np.frombuffer(image[24:32].tobytes(), np.uint64)[0])
+    o = 64 + 32 * n + 4 * nc
+    return [int(x) for x in image[o:o + nc]]
 
 
 def test_windows_slots_streams_and_shapes_do_not_change_the_image(ctx):
@@ -368,3 +432,191 @@ def test_image_file_round_trip(ctx, tmp_path):
     rc, back = mk.ckpt_image_load(path, 3)
     assert rc == 0 and np.array_equal(back.view(), oimg)
     restore_and_compare(ctx, back, table)
+
+
+def test_corrupt_previous_image_is_rejected_like_the_oracle(ctx):
+    """A delta dump against a previous image whose header or tables were
+    damaged fails with the oracle's code (the previous digest table is
+    checked before it is trusted); damage in its payload, which a delta
+    dump never reads, leaves both sides' delta images equal."""
+    c = 4096
+    rng = np.random.default_rng(71)
+    gen = torch.Generator(device=DEV).manual_seed(71)
+    table = _rand_table(rng, gen, 6, c, max_chunks=8)
+    for where in ("header", "records", "crc", "kind", "payload"):
+        prev_g, prev_o, _ = check_parity(ctx, table, c)
+        v = prev_g.view()           # the library's own image bytes, writable
+        n = len(table)
+        nc = int(np.frombuffer(prev_o[24:32].tobytes(), np.uint64)[0])
+        tl = (32 * n + 5 * nc + 15) & ~15
+        pos = {"header": 33, "records": 64 + 8, "crc": 64 + 32 * n + 4 * (nc // 2),
+               "kind": 64 + 32 * n + 4 * nc + nc // 2, "payload": 64 + tl + 100}[where]
+        v[pos] ^= 0x40
+        bad_o = prev_o.copy()
+        bad_o[pos] ^= 0x40
+        orc, oimg = corc.dump(host(table), c, prev=bad_o)
+        rc, img, _ = mk.ckpt_dump(ctx, table, prev=prev_g, opts=mk.make_opts(chunk_size=c))
+        assert rc == orc, (where, rc, orc)
+        if where == "payload":
+            assert rc == 0 and np.array_equal(img.view(), oimg)
+            img.free()
+        else:
+            assert rc == mk.CKPT_ECORRUPT and img is None
+        prev_g.free()
+
+
+def test_fresh_lookback_words_are_cleared():
+    """Look-back status words live in device memory that hipMalloc may hand
+    back from earlier allocations. Device memory is filled with words that
+    read as published inclusive prefixes of the first epoch (value 0, so a
+    dump that trusted them would misplace records, not write out of bounds)
+    and returned to the runtime; a fresh context's first dumps -- whose
+    status buffers may reuse that memory -- still give the oracle's images."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    word = (2 << 62) | (1 << 40)       # inclusive prefix, epoch 1, value 0
+    poison = [torch.full((2 << 20,), word - (1 << 64), dtype=torch.int64, device=DEV) for _ in range(64)]
+    torch.cuda.synchronize()
+    del poison
+    torch.cuda.empty_cache()
+    c2 = mk.ckpt_ctx_create(0, 64 << 20)
+    try:
+        gen = torch.Generator(device=DEV).manual_seed(72)
+        for c, size in ((64, 8 << 20), (4096, 24 << 20), (65536, 40 << 20)):
+            t = torch.randint(0, 256, (size,), dtype=torch.uint8, device=DEV, generator=gen)
+            t[size // 3:size // 2] = 0
+            img, _, _ = check_parity(c2, [(1, t), (2, t[:size // 5].clone())], c)
+            img.free()
+    finally:
+        mk.ckpt_ctx_destroy(c2)
+
+
+def test_strict_verify_restores_and_reports_like_the_oracle(ctx):
+    """strict_verify = 1: a good image restores byte for byte and the re-read
+    stage is timed; a damaged payload gives the oracle's (code, first bad
+    chunk), as without strict mode; a delta applied in place with strict mode
+    re-reads every chunk, UNCHANGED ones included."""
+    c = 16384
+    rng = np.random.default_rng(73)
+    gen = torch.Generator(device=DEV).manual_seed(73)
+    table = _rand_table(rng, gen, 10, c, max_chunks=9)
+    img, oimg, _ = check_parity(ctx, table, c)
+    res = restore_and_compare(ctx, img, table, strict_verify=1)
+    assert res.ns_stage[4] > 0 and res.ns_stage[3] > 0
+    plain = restore_and_compare(ctx, img, table)
+    assert plain.ns_stage[4] == 0
+    bad = oimg.copy()
+    bad[bad.size - 3000] ^= 0x08
+    want = corc.restore(bad, [(i, np.zeros(t.numel(), np.uint8)) for i, t in table])
+    rc, bimg = mk.ckpt_image_import(bad)
+    assert rc == 0
+    for strict in (0, 1):
+        targets = [(i, torch.zeros_like(t)) for i, t in table]
+        rc, r = mk.ckpt_restore(ctx, bimg, targets, opts=mk.make_opts(strict_verify=strict))
+        assert (rc, r.first_bad_chunk) == want and rc == mk.CKPT_ECORRUPT
+    bimg.free()
+    # delta in place, strict
+    prev = [(i, t.clone()) for i, t in table]
+    workloads.mutate_runs(table, seed=74, chunk=c, frac=0.3, run_mean=2)
+    delta, odelta, dres = check_parity(ctx, table, c, prev_gpu=img, prev_oracle=oimg)
+    assert dres.n_unchanged > 0
+    rc, r = mk.ckpt_restore(ctx, delta, prev, opts=mk.make_opts(strict_verify=1))
+    assert rc == 0, (mk.ckpt_strerror(rc), r.first_bad_chunk)
+    assert r.ns_stage[1] > 0 and r.ns_stage[4] > 0
+    torch.cuda.synchronize()
+    for (_, a), (_, b) in zip(table, prev):
+        assert torch.equal(a, b)
+    assert mk.ckpt_restore(ctx, img, table, opts=mk.make_opts(strict_verify=2))[0] == mk.CKPT_EINVAL
+    img.free()
+    delta.free()
+
+
+def test_strict_verify_sees_writes_that_did_not_stick(ctx):
+    """Two allocations of the table restored into the same device memory: each
+    chunk passes the fused check as it is written, but the memory can hold
+    only one of the two contents, so the strict re-read fails (the fused
+    check alone cannot see it)."""
+    c = 65536
+    gen = torch.Generator(device=DEV).manual_seed(75)
+    a = torch.randint(0, 256, (8 * c + 100,), dtype=torch.uint8, device=DEV, generator=gen)
+    b = torch.randint(0, 256, (8 * c + 100,), dtype=torch.uint8, device=DEV, generator=gen)
+    img, _, _ = check_parity(ctx, [(1, a), (2, b)], c)
+    same = torch.zeros_like(a)
+    rc, r = mk.ckpt_restore(ctx, img, [(1, same), (2, same)])
+    assert rc == 0
+    rc, r = mk.ckpt_restore(ctx, img, [(1, same), (2, same)], opts=mk.make_opts(strict_verify=1))
+    assert rc == mk.CKPT_ECORRUPT and r.first_bad_chunk < 18
+    img.free()
+
+
+def test_stage_times_are_reported(ctx):
+    """ckpt_result.ns_stage: the stages each call form runs are timed, the
+    others are 0, and CKPT_OPT_NO_TIMING leaves only the wall times."""
+    c = 65536
+    rng = np.random.default_rng(76)
+    gen = torch.Generator(device=DEV).manual_seed(76)
+    table = _rand_table(rng, gen, 8, c, max_chunks=20)
+    img, res = gpu_dump(ctx, table, chunk_size=c)
+    st = list(res.ns_stage)
+    assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0 and st[4] > 0 and st[5] > 0 and st[7] >= st[4]
+    assert st[1] == res.ns_kernel
+    workloads.mutate_runs(table, seed=77, chunk=c, frac=0.2, run_mean=3)
+    delta, dres = gpu_dump(ctx, table, prev=img, chunk_size=c)
+    st = list(dres.ns_stage)
+    assert all(x > 0 for x in (st[0], st[1], st[2], st[3], st[5], st[7]))
+    rc, r = mk.ckpt_restore(ctx, img, table)
+    assert rc == 0
+    st = list(r.ns_stage)
+    assert st[0] > 0 and st[1] == 0 and st[2] > 0 and st[3] > 0 and st[4] == 0 and st[5] > 0 and st[7] > 0
+    rc, r = mk.ckpt_restore(ctx, delta, table, opts=mk.make_opts(flags=mk.OPT_NO_TIMING))
+    assert rc == 0
+    st = list(r.ns_stage)
+    assert st[1] > 0 and st[3] == 0 and st[5] == 0 and st[7] > 0
+    img.free()
+    delta.free()
+
+
+def test_graph_restore_replays_and_rejects_corrupt_images(ctx):
+    """Batched form, restore side: a full image restores through one captured
+    graph, replayed on new images of the same table (strict mode too); an
+    image whose tables were damaged is rejected by the graph's own
+    validation with the oracle's code and nothing written; a damaged payload
+    gives the oracle's (code, first bad chunk)."""
+    c = 65536
+    rng = np.random.default_rng(78)
+    gen = torch.Generator(device=DEV).manual_seed(78)
+    table = _rand_table(rng, gen, 30, c, max_chunks=6)
+    gopts = dict(flags=mk.OPT_GRAPH)
+    for rep in range(3):
+        if rep:
+            workloads.mutate_runs(table, seed=79 + rep, chunk=c, frac=0.3, run_mean=2)
+        img, oimg, _ = check_parity(ctx, table, c, **gopts)
+        res = restore_and_compare(ctx, img, table, strict_verify=int(rep == 2), **gopts)
+        assert res.windows == 1 and res.ns_stage[3] > 0
+        img.free()
+    img, oimg, _ = check_parity(ctx, table, c)
+    n = len(table)
+    nc = int(np.frombuffer(oimg[24:32].tobytes(), np.uint64)[0])
+    # damaged crc[] entry: the tables digest no longer matches
+    v = img.view()
+    pos = 64 + 32 * n + 4 * (nc // 3)
+    v[pos] ^= 0x01
+    bad_o = oimg.copy()
+    bad_o[pos] ^= 0x01
+    want = corc.restore(bad_o, [(i, np.zeros(t.numel(), np.uint8)) for i, t in table])
+    targets = [(i, torch.full_like(t, 0x5A) if t.numel() else t.clone()) for i, t in table]
+    rc, r = mk.ckpt_restore(ctx, img, targets, opts=mk.make_opts(**gopts))
+    assert (rc, r.first_bad_chunk) == want and rc == mk.CKPT_ECORRUPT
+    torch.cuda.synchronize()
+    assert all(bool((t == 0x5A).all()) for _, t in targets if t.numel())    # nothing written
+    v[pos] ^= 0x01
+    # damaged payload
+    v[v.size - 777] ^= 0x20
+    bad_o = oimg.copy()
+    bad_o[bad_o.size - 777] ^= 0x20
+    want = corc.restore(bad_o, [(i, np.zeros(t.numel(), np.uint8)) for i, t in table])
+    rc, r = mk.ckpt_restore(ctx, img, targets, opts=mk.make_opts(**gopts))
+    assert (rc, r.first_bad_chunk) == want and rc == mk.CKPT_ECORRUPT
+    img.free()

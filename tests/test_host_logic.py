@@ -211,3 +211,29 @@ def test_codec_images_import_and_merge_on_the_host(mklib):
         want = corc.parse(bad)[0]
         rc, h = imp(bad)
         assert rc == want == -4, pos
+
+
+def test_pinned_digest_tables_are_never_evicted():
+    """Eviction of resident digest tables (the library's own rule, compiled
+    for the CPU): the victim is the least recently used table no request has
+    pinned; with every table pinned nothing is evicted."""
+    so = os.path.join(ROOT, "tests", "emu", "libdigest_policy.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I", CSRC, "-o", so,
+                           os.path.join(ROOT, "tests", "emu", "digest_policy.cpp")])
+    L = ctypes.CDLL(so)
+    L.emu_digest_victim.restype = ctypes.c_uint64
+    L.emu_digest_victim.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int]
+    rng = np.random.default_rng(40)
+    for trial in range(300):
+        n = int(rng.integers(1, 40))
+        uids = rng.choice(np.arange(1, 10**6, dtype=np.uint64), n, replace=False)
+        last = rng.permutation(n).astype(np.uint64) + 1
+        pins = (rng.random(n) < rng.random()).astype(np.uint32) * rng.integers(1, 4, n).astype(np.uint32)
+        v = L.emu_digest_victim(uids.ctypes.data, last.ctypes.data, pins.ctypes.data, n)
+        free = pins == 0
+        if not free.any():
+            assert v == 0
+        else:
+            i = int(np.nonzero(uids == v)[0][0])
+            assert pins[i] == 0 and last[i] == last[free].min()

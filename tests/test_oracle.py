@@ -17,7 +17,7 @@ import pytest
 
 from oracle import oracle as corc
 from oracle import spec
-from testlib import decode_input, golden_lines, hw_crc32c
+from testlib import crc_collide as _collide, decode_input, golden_lines, hw_crc32c
 
 OK, EINVAL, ECORRUPT, EMISMATCH, EBASE = 0, -1, -4, -5, -6
 ZERO, DATA, UNCHANGED = 0, 1, 2
@@ -329,44 +329,6 @@ def test_spec_and_c_error_codes_agree():
 
 
 # ------------------------------------------------------------------ forced collision
-def _raw(data):
-    """Raw CRC-32C (no preset, no complement) from the hardware CRC: CRC is affine,
-    so raw(M) = CRC(M) xor CRC(0^|M|)."""
-    return hw_crc32c(data) ^ hw_crc32c(bytes(len(data)))
-
-
-def _collide(orig, modified, pos):
-    """Patch 4 bytes of `modified` at `pos` so that its CRC-32C equals orig's."""
-    n = len(orig)
-    target = _raw(bytes(a ^ b for a, b in zip(orig, modified)))
-    cols = []
-    for bit in range(32):
-        e = bytearray(n)
-        e[pos + bit // 8] = 1 << (bit % 8)
-        cols.append(_raw(bytes(e)))
-    # solve sum(w_i * cols_i) = target over GF(2)
-    rows = [(cols[i], 1 << i) for i in range(32)]
-    basis = {}
-    for v, m in rows:
-        for b in range(31, -1, -1):
-            if not (v >> b) & 1:
-                continue
-            if b in basis:
-                v ^= basis[b][0]; m ^= basis[b][1]
-            else:
-                basis[b] = (v, m)
-                break
-    v, m = target, 0
-    for b in range(31, -1, -1):
-        if (v >> b) & 1:
-            v ^= basis[b][0]; m ^= basis[b][1]
-    assert v == 0
-    out = bytearray(modified)
-    for i in range(4):
-        out[pos + i] ^= (m >> (8 * i)) & 0xFF
-    return bytes(out)
-
-
 def test_forced_crc_collision_is_unchanged_in_both_oracles():
     c = 64
     rng = np.random.default_rng(15)

@@ -56,3 +56,46 @@ def golden_lines(name):
             line = line.strip()
             if line and not line.startswith("#"):
                 yield line.split()
+
+
+def _raw_crc(data):
+    """Raw CRC-32C (no preset, no complement) from the hardware CRC: CRC is affine,
+    so raw(M) = CRC(M) xor CRC(0^|M|)."""
+    return hw_crc32c(data) ^ hw_crc32c(bytes(len(data)))
+
+
+def crc_collide(orig, modified, pos):
+    """Patch 4 bytes of `modified` at `pos` so that its CRC-32C equals orig's
+    (CRC is affine in the message: the 32 single-bit flips of those bytes span
+    the raw CRC's 32-bit space, so the system over GF(2) has a solution).
+    Built on the hardware CRC only, so it shares nothing with the oracle or
+    the GPU library."""
+    n = len(orig)
+    target = _raw_crc(bytes(a ^ b for a, b in zip(orig, modified)))
+    cols = []
+    for bit in range(32):
+        e = bytearray(n)
+        e[pos + bit // 8] = 1 << (bit % 8)
+        cols.append(_raw_crc(bytes(e)))
+    # solve sum(w_i * cols_i) = target over GF(2)
+    basis = {}
+    for v, m in ((cols[i], 1 << i) for i in range(32)):
+        for b in range(31, -1, -1):
+            if not (v >> b) & 1:
+                continue
+            if b in basis:
+                v ^= basis[b][0]
+                m ^= basis[b][1]
+            else:
+                basis[b] = (v, m)
+                break
+    v, m = target, 0
+    for b in range(31, -1, -1):
+        if (v >> b) & 1:
+            v ^= basis[b][0]
+            m ^= basis[b][1]
+    assert v == 0
+    out = bytearray(modified)
+    for i in range(4):
+        out[pos + i] ^= (m >> (8 * i)) & 0xFF
+    return bytes(out)
