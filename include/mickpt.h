@@ -177,6 +177,28 @@ void ckpt_ctx_destroy(ckpt_ctx* ctx);
 int  ckpt_dump(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* prev,
                ckpt_image** out, const ckpt_opts* opts, void* stream, ckpt_result* res);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ckpt_dump into fixed
+ * buffers. The image (the same bytes ckpt_dump would return for these
+ * arguments) is written to the caller's host buffer out[0, out_cap) and its
+ * length to *out_len; the device work runs in one array of 128 MiB per GPU
+ * that the library holds from the first context on that GPU until the
+ * process ends. Nothing is allocated: no device, pinned or pageable image
+ * memory, streams or events (ckpt_ctx_create made those).
+ * Limits (CKPT_ELIMIT, returned before any work is queued): at most 16,384
+ * allocations and 2^20 chunks in the table and in prev, and a chunk size
+ * whose staging slot (about 52 MiB) holds at least one chunk; larger
+ * payloads run as several windows on two slots. CKPT_OPT_PER_ALLOC,
+ * CKPT_OPT_GRAPH and CKPT_OPT_CODEC are not accepted (CKPT_EINVAL). An out
+ * buffer too small for the image gives CKPT_ENOMEM and *out_len = 0. The
+ * call keeps nothing between calls except the array's contents: every call
+ * clears what it needs at zero. Calls on one GPU are serialized within the
+ * process; calls from several processes on one GPU each have their own
+ * array. On failure *out_len = 0 and the contents of out are unspecified. */
+int  ckpt_dump_into(ckpt_ctx* ctx, const ckpt_alloc_table* table, const ckpt_image* prev, void* out,
+                    uint64_t out_cap, uint64_t* out_len, const ckpt_opts* opts, void* stream,
+                    ckpt_result* res);
+
 /* ------------------------------------------------------------------ restore */
 /* Restore (section 3.1.1 restore action; section 6 deterministic restore).
  * Validates the image (header and tables digests, structure), checks that

@@ -291,6 +291,9 @@ struct NaCall {
     NaDevice* dev;
     uint64_t* len;   // receives the image length
 };
+// Address of the array of `device`, looked up once per device with that
+// device current (the context's set-up calls it).
+hipError_t na_setup(int device);
 // The context's lock must be held. Fails with CKPT_ELIMIT beyond the array's
 // limits, before any work is queued.
 int dump_fixed(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, const ckpt_opts* o,

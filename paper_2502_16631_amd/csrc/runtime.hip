@@ -489,9 +489,10 @@ extern "C" int ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_order, hipEventDisableTiming);
     if (e == hipSuccess) e = ensure_copy_streams(c, 2);
     if (e == hipSuccess) e = ensure_events(c, 16);
-    if (e == hipSuccess) e = ensure_tevents(c, 16);
+    if (e == hipSuccess) e = ensure_tevents(c, 4 * kCodecPieces);
     if (e == hipSuccess) e = ensure_hsmall(c, 4096);
     for (int i = 0; i < 8 && e == hipSuccess; ++i) e = hipEventCreate(&c->sev[i]);
+    if (e == hipSuccess) e = na_setup(device);
     c->hconsts = new EngineConsts();
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1530,6 +1531,54 @@ int mk::dump_fixed(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image*
     const int rc = dump_run(c, table, prev, nullptr, o, stream, res, nullptr, &na);
     if (rc != CKPT_OK) drain(c);
     return rc;
+}
+
+// ------------------------------------------------------------ dump into fixed buffers
+// The device array of every fixed-buffer dump (kNaBytes on each GPU the
+// library runs on, held until the process ends). Its name is a host-side
+// stand-in in host code: each GPU's copy has its own device address, taken
+// once per device with hipGetSymbolAddress (na_setup) and used everywhere
+// host code needs the array's memory.
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+NaDevice g_na[kNaMaxDevices];
+std::mutex g_na_mu;
+}  // namespace
+
+// The array of `device` (which must be current); its address is looked up
+// on the first call for that device.
+hipError_t mk::na_setup(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_na_mu);
+    NaDevice& nd = g_na[device];
+    if (nd.ptr) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    if (!p) return hipErrorInvalidSymbol;
+    nd.ptr = static_cast<uint8_t*>(p);
+    nd.status.buf.attach(nd.ptr + kNaStatus, 8 * kNaStatusWords);
+    return hipSuccess;
+}
+
+extern "C" int ckpt_dump_into(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* prev, void* out,
+                              uint64_t out_cap, uint64_t* out_len, const ckpt_opts* o, void* stream,
+                              ckpt_result* res) {
+    fill_result(res);
+    if (out_len) *out_len = 0;
+    if (!c || !table || !out || !out_len) return CKPT_EINVAL;
+    if (c->device < 0 || c->device >= kNaMaxDevices) return CKPT_EINVAL;
+    NaDevice& nd = g_na[c->device];
+    std::lock_guard<std::mutex> g(c->mu);
+    std::lock_guard<std::mutex> g2(nd.mu);
+    if (!nd.ptr) return CKPT_EHIP;   // the context's set-up found no array (ckpt_ctx_create failed then)
+    const NaCall na{static_cast<uint8_t*>(out), out_cap, &nd, out_len};
+    return dump_fixed(c, table, prev, o, stream, res, na);
 }
 
 // ------------------------------------------------------------ restore

@@ -102,6 +102,9 @@ def lib():
         L.ckpt_dump.argtypes = [vp, ctypes.POINTER(ckpt_alloc_table), vp, ctypes.POINTER(vp),
                                 ctypes.POINTER(ckpt_opts), vp, ctypes.POINTER(ckpt_result)]
         L.ckpt_dump.restype = ctypes.c_int
+        L.ckpt_dump_into.argtypes = [vp, ctypes.POINTER(ckpt_alloc_table), vp, vp, _u64, ctypes.POINTER(_u64),
+                                     ctypes.POINTER(ckpt_opts), vp, ctypes.POINTER(ckpt_result)]
+        L.ckpt_dump_into.restype = ctypes.c_int
         L.ckpt_restore.argtypes = [vp, vp, ctypes.POINTER(ckpt_alloc_table), ctypes.POINTER(ckpt_opts), vp,
                                    ctypes.POINTER(ckpt_result)]
         L.ckpt_restore.restype = ctypes.c_int
@@ -265,6 +268,18 @@ def ckpt_dump(ctx, table, prev=None, opts=None, stream=None):
                          ctypes.byref(out), ctypes.byref(opts) if opts is not None else None,
                          _stream(stream), ctypes.byref(res))
     return rc, (Image(out.value) if rc == 0 else None), res
+
+
+def ckpt_dump_into(ctx, table, out, prev=None, opts=None, stream=None):
+    """Dump into the caller's host buffer `out` (a writable uint8 numpy
+    array); nothing is allocated. Returns (rc, image length, result)."""
+    tab, keep = _table(table)
+    n = _u64()
+    res = ckpt_result()
+    rc = lib().ckpt_dump_into(ctx, ctypes.byref(tab), prev.handle if prev is not None else None,
+                              ctypes.c_void_p(out.ctypes.data), int(out.nbytes), ctypes.byref(n),
+                              ctypes.byref(opts) if opts is not None else None, _stream(stream), ctypes.byref(res))
+    return rc, n.value, res
 
 
 def ckpt_restore(ctx, image, table, opts=None, stream=None):
