@@ -118,9 +118,10 @@ def copy_kernel_rate(torch, nbytes=4 << 30, reps=5):
 
 def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
     """Read + write GB/s of the hand-written 128-bit copy kernel
-    (csrc/copyprobe.hip, four blocks in flight per thread, grid-stride),
-    best over a sweep of grid sizes, work-group widths and plain /
-    non-temporal stores: the measured copy ceiling of this GPU."""
+    (csrc/copyprobe.hip: contiguous tiles per work-group, four or eight
+    blocks in flight per thread), best over a sweep of grid sizes,
+    work-group widths, loads in flight and plain / non-temporal stores: the
+    measured copy ceiling of this GPU."""
     import ctypes
     so = os.path.join(ROOT, "paper_2502_16631_amd", "libmkcopy.so")
     L = ctypes.CDLL(so)
@@ -133,14 +134,15 @@ def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
     best = None
     for blocks in (1024, 2048, 4096, 8192, 16384):
         for threads in (256, 512, 1024):
-            for nt in (0, 1):
+            for nt in (0, 1, 2, 3):
                 ms = ctypes.c_float(0)
                 rc = L.mkcopy_run(dst.data_ptr(), src.data_ptr(), nbytes, blocks, threads, nt, reps, ctypes.byref(ms))
                 if rc != 0:
                     raise RuntimeError("copy kernel: hip error %d" % rc)
                 gbs = 2.0 * nbytes / (ms.value * 1e-3) / 1e9
                 if best is None or gbs > best["GBps"]:
-                    best = {"GBps": round(gbs, 1), "blocks": blocks, "threads": threads, "nt_stores": bool(nt)}
+                    best = {"GBps": round(gbs, 1), "blocks": blocks, "threads": threads, "nt_stores": bool(nt & 1),
+                            "loads_in_flight": 8 if nt & 2 else 4}
     del src, dst
     torch.cuda.synchronize()
     return best
@@ -258,8 +260,14 @@ def main():
     ap.add_argument("--path", default="/tmp/mickpt_bench.img", help="storage: image file (removed afterwards)")
     ap.add_argument("--io-threads", type=int, default=8, help="storage: file I/O threads")
     ap.add_argument("--scale", type=float, default=1.0, help="scale the total bytes of the non-plain forms")
-    ap.add_argument("--duration", type=float, default=30.0, help="serve: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=600.0, help="serve: seconds of arrivals (10 minutes)")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: aggregate requests per second")
+    ap.add_argument("--serve-state", type=float, default=180e9,
+                    help="serve: total bytes of the 32 tenants' device states (the log-uniform draw is rescaled "
+                         "to it; the tenants' last images must fit host memory)")
+    ap.add_argument("--serve-leg", default="served", choices=["served", "baseline"],
+                    help="serve: the request loop, or the same trace through plain per-allocation calls one "
+                         "request at a time")
     ap.add_argument("--forms", type=int, default=1,
                     help="plain form: also run the incremental and batched forms (compact, 1 + 3 steps each) and "
                          "report them under 'forms' (0 = skip)")

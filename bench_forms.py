@@ -158,133 +158,235 @@ def batched(args, torch, mk, link):
     }
 
 
-def serve(args, torch, mk, link):
-    """32 tenants with device states log-uniform in [100 MB, 8 GB] (scaled to
-    ~24 GB in total, so that every tenant's last image and the images of
-    the requests in flight fit the host's pinned-memory limit (64 GiB on the
-    machines measured); kinds cycle DL-like / HPC-like / random), Poisson
-    arrivals at `rate` requests per second for `duration` seconds, uniform
-    tenant, 50 % dumps (half of them incremental after 5 % of the tenant's
-    chunks were rewritten) and 50 % restores of the tenant's last image; a
-    tenant's requests run one at a time. Latency is arrival to completion."""
-    rng = np.random.default_rng(5)
-    n_t = 32
-    sizes = workloads.loguniform_sizes(n_t, 100 * 10**6, 8 * 10**9, int(24e9 * args.scale), 1 << 20, seed=5)
+def _rss_gb():
+    """Resident host memory of this process (pinned image memory included)."""
+    try:
+        with open("/proc/self/status") as fh:
+            for line in fh:
+                if line.startswith("VmRSS:"):
+                    return int(line.split()[1]) * 1024 / 1e9
+    except OSError:
+        pass
+    return float("nan")
+
+
+def _tenant_states(torch, n_t, total, seed=5):
+    """32 tenant device states, sizes log-uniform in [100 MB, 40 GB] rescaled
+    to `total` bytes (the c5 draw), kinds cycling DL-like (bf16 weights
+    N(0, 0.02) and fp32 optimizer state N(0, 1e-3)), HPC-like (the HPC
+    image's zero-run process) and fragmented-like (random bytes with zero
+    blocks)."""
+    sizes = workloads.loguniform_sizes(n_t, 100 * 10**6, 40 * 10**9, int(total), 1 << 20, seed=seed)
     tenants = []
     for t, size in enumerate(sizes):
         kind = t % 3
-        if kind == 0:       # DL-like: bf16 weights and fp32 optimizer state
+        if kind == 0:
             gen = torch.Generator(device="cuda").manual_seed(100 + t)
             w = torch.empty(size // 4, dtype=torch.bfloat16, device="cuda").normal_(0, 0.02, generator=gen)
             m = torch.empty(size // 4, dtype=torch.float32, device="cuda").normal_(0, 1e-3, generator=gen)
             table = [(0, w), (1, m)]
-        elif kind == 1:     # HPC-like: zero runs
+        elif kind == 1:
             table, _ = workloads.hpc_state("cuda", seed=100 + t, total=size, n=8, chunk=C)
-        else:               # random bytes with zero blocks
+        else:
             table = workloads.fragmented_state("cuda", seed=100 + t, total=size, n=16)
-        tenants.append({"table": table, "N": _nbytes(table), "last": None, "busy": None, "backlog": [],
-                        "stale": False})
+        # two clustered dirty sets (5 % of chunks, runs of mean 16), used in turn
+        plans = [workloads.dirty_chunks(table, seed=1000 * t + k, chunk=C, frac=0.05, run_mean=16) for k in range(2)]
+        tenants.append({"table": table, "N": _nbytes(table), "kind": ("DL", "HPC", "fragmented")[kind],
+                        "plans": plans, "mut": 0})
+    return tenants
+
+
+def _trace(rate, duration, n_t, seed=5):
+    """Poisson arrivals (aggregate rate), uniform tenant; 50 % restores of the
+    tenant's last image, 25 % full dumps, 25 % delta dumps (after 5 % of the
+    tenant's chunks are rewritten)."""
+    rng = np.random.default_rng(seed)
+    out, tt = [], 0.0
+    while True:
+        tt += rng.exponential(1.0 / rate)
+        if tt > duration:
+            return out
+        r = rng.random()
+        out.append((tt, int(rng.integers(0, n_t)), "restore" if r < 0.5 else ("delta" if r < 0.75 else "full")))
+
+
+def _lat_summary(lat):
+    return {"p50_ms": round(_pct(lat, 50) * 1e3, 2) if lat else None,
+            "p99_ms": round(_pct(lat, 99) * 1e3, 2) if lat else None,
+            "max_ms": round(max(lat) * 1e3, 2) if lat else None}
+
+
+def serve(args, torch, mk, link):
+    """The served form on config c5: 32 tenants whose device states are drawn
+    log-uniform in [100 MB, 40 GB] and rescaled to --serve-state bytes in
+    total (host memory for the tenants' last images bounds the scale: the
+    draw totals ~213 GB), a Poisson trace of --rate requests per second for
+    --duration seconds. --serve-leg served: the trace through the request
+    loop (16 lanes, 64 GB staging budget); baseline: the same trace through
+    plain calls with per-allocation launches, one request at a time in
+    arrival order (the plain per-allocation path), stopped 25 % past the
+    trace's end (requests not done by then are counted at their latency
+    so far, a lower bound). A tenant's requests run one at a time in both.
+    Latency is arrival to completion."""
+    n_t = 32
+    leg = args.serve_leg
+    tenants = _tenant_states(torch, n_t, args.serve_state)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()     # the generators' temporaries back to the device
     N_all = sum(t["N"] for t in tenants)
-    ctx = mk.ckpt_ctx_create(0, 64 << 30)
+    # the context's own staging (base dumps, the baseline's plain calls): 8 GiB, windows of 2 GiB
+    # for the large tenants; the served loop admits against its own 64 GB budget
+    ctx = mk.ckpt_ctx_create(0, 8 << 30)
     opts = mk.make_opts(chunk_size=C)
+    t0 = time.perf_counter()
     for t in tenants:
         rc, img, _ = mk.ckpt_dump(ctx, t["table"], opts=opts)
-        assert rc == 0
+        assert rc == 0, mk.ckpt_strerror(rc)
         t["last"] = img
-    _log("tenants ready: %.1f GB in %d tenants" % (N_all / 1e9, n_t))
-    srv = mk.ckpt_serve_create(ctx, 16, 64 << 30)
-    # arrivals
-    arrivals, tt = [], 0.0
-    while True:
-        tt += rng.exponential(1.0 / args.rate)
-        if tt > args.duration:
-            break
-        r = rng.random()
-        arrivals.append((tt, int(rng.integers(0, n_t)), "restore" if r < 0.5 else ("delta" if r < 0.75 else "full")))
-    lat, done_bytes, n_done, n_fail = [], 0, 0, 0
-    fail_codes = {}
-    kinds_done = {"restore": 0, "delta": 0, "full": 0}
-    inflight = {}
+    _log("tenants ready: %.1f GB of state in %d tenants, base images %.1f GB (%.1f s), host RSS %.1f GB"
+         % (N_all / 1e9, n_t, sum(t["last"].nbytes() for t in tenants) / 1e9, time.perf_counter() - t0, _rss_gb()))
+    arrivals = _trace(args.rate, args.duration, n_t)
+    stream = torch.cuda.Stream()
+
+    def mutate(ten):
+        with torch.cuda.stream(stream):
+            workloads.apply_dirty(ten["table"], ten["plans"][ten["mut"] % 2], chunk=C)
+        ten["mut"] += 1
+        stream.synchronize()
+
+    lat, by_kind, fails = [], {"restore": 0, "delta": 0, "full": 0}, {}
+    done_bytes, link_bytes = 0, 0
     t_start = time.perf_counter()
-    ai = 0
-    old_images = []
+    last_log = t_start
+    st = None
+    if leg == "served":
+        srv = mk.ckpt_serve_create(ctx, 16, 64 << 30)
+        busy, backlog, inflight = [None] * n_t, [[] for _ in range(n_t)], {}
+        ai = 0
 
-    def submit(tid, kind, t_arr):
-        ten = tenants[tid]
-        if ten["stale"]:
-            # a failed dump left the state ahead of the last image: take a full one
-            kind = "full"
-        if kind == "restore":
-            rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, ten["table"], img=ten["last"], tenant=tid)
-        else:
-            prev = None
-            if kind == "delta":
-                workloads.mutate_runs(ten["table"], seed=int(rng.integers(1 << 30)), chunk=C, frac=0.05, run_mean=16)
-                torch.cuda.synchronize()
-                prev = ten["last"]
-            rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, ten["table"], prev=prev, tenant=tid)
-        assert rc == 0
-        ten["busy"] = tk
-        inflight[tk] = (tid, kind, t_arr)
-
-    while ai < len(arrivals) or inflight:
-        now = time.perf_counter() - t_start
-        while ai < len(arrivals) and arrivals[ai][0] <= now:
-            t_arr, tid, kind = arrivals[ai]
-            ai += 1
-            if tenants[tid]["busy"] is None:
-                submit(tid, kind, t_arr)
-            else:
-                tenants[tid]["backlog"].append((kind, t_arr))
-        for tk in list(inflight):
-            done, rc, img, _ = mk.ckpt_serve_poll(srv, tk)
-            if not done:
-                continue
-            tid, kind, t_arr = inflight.pop(tk)
+        def submit(tid, kind, t_arr):
             ten = tenants[tid]
-            ten["busy"] = None
+            if ten.get("stale"):
+                kind = "full"
+            if kind == "restore":
+                rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, ten["table"], img=ten["last"], tenant=tid)
+            else:
+                prev = None
+                if kind == "delta":
+                    mutate(ten)
+                    prev = ten["last"]
+                rc, tk = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, ten["table"], prev=prev, tenant=tid)
+            assert rc == 0
+            busy[tid] = tk
+            inflight[tk] = (tid, kind, t_arr)
+
+        while ai < len(arrivals) or inflight:
+            now = time.perf_counter() - t_start
+            while ai < len(arrivals) and arrivals[ai][0] <= now:
+                t_arr, tid, kind = arrivals[ai]
+                ai += 1
+                if busy[tid] is None:
+                    submit(tid, kind, t_arr)
+                else:
+                    backlog[tid].append((kind, t_arr))
+            for tk in list(inflight):
+                done, rc, img, _ = mk.ckpt_serve_poll(srv, tk)
+                if not done:
+                    continue
+                tid, kind, t_arr = inflight.pop(tk)
+                ten = tenants[tid]
+                busy[tid] = None
+                lat.append(time.perf_counter() - t_start - t_arr)
+                if rc != 0:
+                    fails[mk.ckpt_strerror(rc)] = fails.get(mk.ckpt_strerror(rc), 0) + 1
+                    if kind != "restore":
+                        ten["stale"] = True
+                else:
+                    by_kind[kind] += 1
+                    done_bytes += ten["N"]
+                    if img is not None:
+                        link_bytes += img.nbytes()
+                        ten["last"] = img     # the old image is freed with its last reference
+                        ten["stale"] = False
+                    else:
+                        link_bytes += ten["last"].nbytes()
+                if backlog[tid]:
+                    k2, ta2 = backlog[tid].pop(0)
+                    submit(tid, k2, ta2)
+            if time.perf_counter() - last_log > 30:
+                last_log = time.perf_counter()
+                _log("served: t=%.0f s, %d of %d arrived, %d done, %d in flight, host RSS %.1f GB" % (
+                    now, ai, len(arrivals), len(lat), len(inflight), _rss_gb()))
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t_start
+        st = mk.ckpt_serve_stats(srv)
+        mk.ckpt_serve_destroy(srv)
+        unfinished = 0
+    else:
+        popts = mk.make_opts(chunk_size=C, flags=mk.OPT_PER_ALLOC)
+        t_stop = args.duration * 1.25
+        unfinished = 0
+        free_at = [0.0] * n_t      # a tenant's requests one at a time (all of them are, here)
+        for t_arr, tid, kind in arrivals:
+            now = time.perf_counter() - t_start
+            if now > t_stop:
+                lat.append(now - t_arr)    # not done by the stop: latency so far (a lower bound)
+                unfinished += 1
+                continue
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            ten = tenants[tid]
+            if ten.get("stale"):
+                kind = "full"
+            if kind == "restore":
+                rc, _ = mk.ckpt_restore(ctx, ten["last"], ten["table"], opts=popts)
+                img = None
+            else:
+                prev = None
+                if kind == "delta":
+                    mutate(ten)
+                    prev = ten["last"]
+                rc, img, _ = mk.ckpt_dump(ctx, ten["table"], prev=prev, opts=popts)
             lat.append(time.perf_counter() - t_start - t_arr)
             if rc != 0:
-                n_fail += 1
+                fails[mk.ckpt_strerror(rc)] = fails.get(mk.ckpt_strerror(rc), 0) + 1
                 if kind != "restore":
                     ten["stale"] = True
-                fail_codes[mk.ckpt_strerror(rc)] = fail_codes.get(mk.ckpt_strerror(rc), 0) + 1
+                continue
+            by_kind[kind] += 1
+            done_bytes += ten["N"]
+            if img is not None:
+                link_bytes += img.nbytes()
+                ten["last"] = img
+                ten["stale"] = False
             else:
-                n_done += 1
-                kinds_done[kind] += 1
-                done_bytes += ten["N"]
-                if img is not None:
-                    old_images.append(ten["last"])
-                    ten["last"] = img
-                    ten["stale"] = False
-            if ten["backlog"]:
-                k2, ta2 = ten["backlog"].pop(0)
-                submit(tid, k2, ta2)
-        # images no request refers to any more
-        busy_imgs = {id(tenants[i]["last"]) for i in range(n_t)}
-        old_images = [im for im in old_images if id(im) in busy_imgs]
-        time.sleep(0.0005)
-    wall = time.perf_counter() - t_start
-    st = mk.ckpt_serve_stats(srv)
-    mk.ckpt_serve_destroy(srv)
+                link_bytes += ten["last"].nbytes()
+            if time.perf_counter() - last_log > 30:
+                last_log = time.perf_counter()
+                _log("baseline: t=%.0f s, %d of %d done, host RSS %.1f GB" % (
+                    time.perf_counter() - t_start, len(lat), len(arrivals), _rss_gb()))
+        wall = time.perf_counter() - t_start
     mk.ckpt_ctx_destroy(ctx)
-    return {
-        "metric": "served dump/restore throughput and p50/p99 latency at 1 GPU", "form": "serve",
-        "value": round(done_bytes / wall / 1e9, 3), "unit": "GB/s (logical, completed requests)",
-        "config": {"workload": "%d tenants, %.1f GB of device state, Poisson %.1f req/s for %.0f s"
-                               % (n_t, N_all / 1e9, args.rate, args.duration), "chunk": C,
-                   "staging_budget": 64 << 30, "max_active": 16},
-        "requests": len(arrivals), "completed": n_done, "failed": n_fail, "fail_codes": fail_codes,
-        "by_kind": kinds_done,
-        "latency_p50_ms": round(_pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(_pct(lat, 99) * 1e3, 2),
-        "server_p50_ms": round(st.p50_ns / 1e6, 2), "server_p99_ms": round(st.p99_ns / 1e6, 2),
-        "server_mean_wait_ms": round(st.mean_wait_ns / 1e6, 2),
-        "merged_launches": st.launches, "max_batch": st.max_batch,
-        "link_GBps": round(st.bytes_link / wall / 1e9, 3),
-        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
-        "wall_s": round(wall, 2),
+    offered = sum(tenants[tid]["last"].nbytes() for _, tid, _ in arrivals) / max(args.duration, 1e-9)
+    out = {
+        "metric": "served dump/restore throughput and p50/p99 latency at 1 GPU", "form": "serve", "leg": leg,
+        "value": round(done_bytes / wall / 1e9, 3), "unit": "GB/s (logical state of completed requests)",
+        "config": {"workload": "%d tenants, %.1f GB of device state (log-uniform [100 MB, 40 GB] rescaled), "
+                               "Poisson %.1f req/s for %.0f s" % (n_t, N_all / 1e9, args.rate, args.duration),
+                   "tenant_GB": [round(t["N"] / 1e9, 2) for t in tenants], "chunk": C,
+                   "staging_budget": 64 << 30, "context_staging": 8 << 30, "max_active": 16},
+        "requests": len(arrivals), "completed_ok": sum(by_kind.values()), "failed": sum(fails.values()),
+        "fail_codes": fails, "unfinished_at_stop": unfinished, "by_kind": by_kind,
+        "latency": _lat_summary(lat), "link_GBps": round(link_bytes / wall / 1e9, 3),
+        "offered_link_GBps_approx": round(offered / 1e9, 2),
+        "link_measured_GBps": {k: round(v, 2) for k, v in link.items()}, "wall_s": round(wall, 2),
     }
+    if st is not None:
+        out["server"] = {"p50_ms": round(st.p50_ns / 1e6, 2), "p99_ms": round(st.p99_ns / 1e6, 2),
+                         "mean_wait_ms": round(st.mean_wait_ns / 1e6, 2), "max_wait_ms": round(st.max_wait_ns / 1e6, 2),
+                         "merged_launches": st.launches, "max_batch": st.max_batch,
+                         "host_copies": st.host_copies, "host_copy_GB": round(st.host_copy_bytes / 1e9, 2)}
+    return out
 
 
 def ondemand(args, torch, mk, link):

@@ -336,6 +336,9 @@ typedef struct {
     uint64_t max_batch;              /* most requests sharing one launch                          */
     uint64_t p50_ns, p99_ns;         /* latency percentiles, submit to completion                 */
     uint64_t mean_wait_ns;           /* mean wait for admission                                   */
+    uint64_t max_wait_ns;            /* longest wait for admission                                */
+    uint64_t host_copies;            /* payload copies of pageable images made by host workers    */
+    uint64_t host_copy_bytes;        /* their bytes                                               */
 } ckpt_server_stats;
 /* Create a server that drives ctx from its own thread (other calls on ctx
  * are serialized with it) with at most max_active requests in flight

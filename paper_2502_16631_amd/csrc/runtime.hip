@@ -72,21 +72,20 @@ struct PinnedPool {
             }
         }
         void* p = nullptr;
-        if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) {
-            // A handled failure must not stay behind as the thread's last HIP
-            // error (the caller's next error check would report it).
+        // pinned memory is limited per process: on a failure give cached
+        // buffers back, largest first, until the allocation succeeds or none
+        // is left (a handled failure must not stay behind as the thread's
+        // last HIP error: the caller's next error check would report it)
+        for (;;) {
+            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) == hipSuccess) break;
             (void)hipGetLastError();
-            // pinned memory is limited: give back every cached buffer and retry once
-            {
-                std::lock_guard<std::mutex> g(mu);
-                for (auto& kv : free_) hipHostFree(kv.second);
-                free_.clear();
-                cached = 0;
-            }
-            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
+            p = nullptr;
+            std::lock_guard<std::mutex> g(mu);
+            if (free_.empty()) return nullptr;
+            auto last = std::prev(free_.end());
+            hipHostFree(last->second);
+            cached -= last->first;
+            free_.erase(last);
         }
         *got = cap;
         return p;

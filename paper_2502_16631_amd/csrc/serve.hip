@@ -17,6 +17,16 @@
 // deltas, then windows (H2D copy -> kernel), then the per-allocation check.
 // Tenants' digest tables stay resident in the context (keyed by image) for
 // their incremental dumps.
+//
+// Host memory. A copy between the device and a pageable host image returns
+// only once it is done (the runtime stages it through pinned buffers on the
+// calling thread), and so would stall every request on the scheduler
+// thread. Such copies, and the allocation of dump images, go to a pool of
+// host worker threads (each with a stream of its own); the scheduler learns
+// of their completion from per-lane flags instead of events. Dump images
+// are pinned while the pinned pool grants them (the driver pins a limited
+// amount per process), pageable beyond. Small tables of pageable images go
+// through a pinned bounce buffer of the lane.
 #include <hip/hip_runtime.h>
 
 #include <stdlib.h>
@@ -24,6 +34,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <thread>
 #include <unordered_set>
 
@@ -36,11 +47,31 @@ namespace {
 
 constexpr uint64_t kDefaultSlot = 256ull << 20;
 
+// Flags a lane's host work reports through (one value each, set by a
+// worker thread with release order once the work is done): the window whose
+// copy out of dump slot 0 / 1 has completed (+1), the window whose payload is
+// in restore slot 0 / 1 (+1), the dump image allocated (1); kTaskFailed on
+// failure. All are cleared when a request is given the lane.
+enum { kFlDown0 = 0, kFlUp0 = 2, kFlAlloc = 4, kLaneFlags = 5 };
+constexpr uint64_t kTaskFailed = ~0ull;
+
 struct Lane {
     DevBuf descs, arc, kinds, ctl, off, wb, staging, dig, prevcrc, amap;
     StatusBuf status;
     uint8_t* hs = nullptr;   // pinned: per-window payload lengths / offsets, digests, flags
     uint64_t hs_cap = 0;
+    uint8_t* ht = nullptr;   // pinned bounce buffer for the tables of pageable images
+    uint64_t ht_cap = 0;
+    std::atomic<uint64_t>* fl = nullptr;   // kLaneFlags flags (owned by the server)
+    hipError_t ensure_ht(uint64_t n) {
+        if (n <= ht_cap) return hipSuccess;
+        if (ht) hipHostFree(ht);
+        ht = nullptr;
+        ht_cap = 0;
+        hipError_t e = hipHostMalloc((void**)&ht, n, hipHostMallocDefault);
+        if (e == hipSuccess) ht_cap = n;
+        return e;
+    }
     std::vector<hipEvent_t> ev;   // per window: kernel done (dump) or copy done (restore)
     hipEvent_t slot_ev[2] = {nullptr, nullptr};   // dump: copy of the slot done; restore: kernel done
     hipEvent_t fin = nullptr;
@@ -74,10 +105,11 @@ struct Lane {
         for (hipEvent_t e : slot_ev) if (e) hipEventDestroy(e);
         if (fin) hipEventDestroy(fin);
         if (hs) hipHostFree(hs);
+        if (ht) hipHostFree(ht);
     }
 };
 
-enum Phase { kQueued, kValidate, kVerify, kRun, kFinal, kDone };
+enum Phase { kQueued, kAlloc, kValidate, kVerify, kRun, kFinal, kDrain, kDone };
 
 struct Req {
     uint64_t ticket = 0;
@@ -104,6 +136,22 @@ struct Req {
     uint64_t copied = 0;       // dump: windows whose D2H copy is enqueued
     uint64_t pos = 0;          // dump: payload bytes so far
     uint64_t nu = 0;           // restore: UNCHANGED chunks
+    bool pinned = true;        // the host image (dump: out, restore: img) is pinned
+    uint64_t alloc_bytes = 0;  // dump: image size to allocate
+    int drain_rc = 0;          // kDrain: the result once the request's host tasks are done
+    std::atomic<uint32_t> tasks{0};   // host tasks queued or running for this request
+};
+
+// Host work for the worker threads.
+struct HostTask {
+    enum Kind { kD2H, kH2D, kAlloc } kind;
+    Req* r;
+    void* dst;
+    const void* src;
+    uint64_t n;
+    hipEvent_t after;              // device work to wait for first (nullptr: none)
+    std::atomic<uint64_t>* flag;
+    uint64_t value;                // stored to *flag when done
 };
 
 }  // namespace
@@ -127,8 +175,16 @@ struct ckpt_server {
     uint64_t in_system = 0;                    // submitted and not completed
     // stats
     uint64_t submitted = 0, completed = 0, failed = 0, bytes_logical = 0, bytes_link = 0, launches = 0,
-             max_batch = 0, wait_sum = 0;
+             max_batch = 0, wait_sum = 0, max_wait = 0;
+    std::atomic<uint64_t> host_copies{0}, host_copy_bytes{0};
     std::vector<uint64_t> lat;
+    // host workers
+    std::unique_ptr<std::atomic<uint64_t>[]> flags;   // kLaneFlags per lane
+    std::vector<std::thread> workers;
+    std::mutex tmu;
+    std::condition_variable tcv;
+    std::deque<HostTask> tasks;
+    bool tstop = false;
 };
 
 namespace {
@@ -158,10 +214,99 @@ void finish(ckpt_server* s, Req* r, int rc) {
         s->bytes_link += kHeader + r->tl + (r->rq.kind == CKPT_REQ_DUMP ? r->pos : r->v.D);
     }
     s->lat.push_back(r->t_done - r->t_submit);
-    s->wait_sum += (r->t_admit ? r->t_admit : r->t_done) - r->t_submit;
+    const uint64_t wait = (r->t_admit ? r->t_admit : r->t_done) - r->t_submit;
+    s->wait_sum += wait;
+    s->max_wait = std::max(s->max_wait, wait);
     s->in_system--;
     r->phase = kDone;
     s->done_cv.notify_all();
+}
+
+// A request that failed after admission: it ends (kDone) once no host task
+// of it is queued or running and the server's streams have drained, so that
+// nothing still reads or writes its lane when the lane is handed on.
+void fail_req(ckpt_server* s, Req* r, int rc) {
+    (void)s;
+    if (r->phase == kDrain || r->phase == kDone) return;
+    r->drain_rc = rc;
+    r->phase = kDrain;
+}
+
+void drain_step(ckpt_server* s, Req* r) {
+    if (r->tasks.load(std::memory_order_acquire) != 0) return;
+    hipStream_t ss[] = {s->s_dump, s->s_rest, s->s_up, s->s_down};
+    for (hipStream_t x : ss) (void)hipStreamSynchronize(x);
+    (void)hipGetLastError();
+    finish(s, r, r->drain_rc);
+}
+
+// Queue host work for the workers. The flag is cleared first; the task
+// counts as the request's until the worker is done with it.
+void host_task(ckpt_server* s, HostTask t) {
+    t.r->tasks.fetch_add(1, std::memory_order_acq_rel);
+    t.flag->store(0, std::memory_order_relaxed);
+    {
+        std::lock_guard<std::mutex> g(s->tmu);
+        s->tasks.push_back(t);
+    }
+    s->tcv.notify_one();
+}
+
+// A worker: takes tasks in order. A copy that involves pageable memory runs
+// synchronously on the worker's own stream; the flag is stored (release)
+// before the request's task count drops, and the worker touches neither
+// after that.
+void worker(ckpt_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    hipStream_t st = nullptr;
+    const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (;;) {
+        HostTask t;
+        {
+            std::unique_lock<std::mutex> g(s->tmu);
+            s->tcv.wait(g, [s] { return s->tstop || !s->tasks.empty(); });
+            if (s->tasks.empty()) break;   // stopping, and nothing left to do
+            t = s->tasks.front();
+            s->tasks.pop_front();
+        }
+        uint64_t v = t.value;
+        Req* r = t.r;
+        if (t.kind == HostTask::kAlloc) {
+            ckpt_image* im = image_new(t.n);   // the image of a dump
+            r->out = im;   // read by the scheduler only after the flag
+            if (!im) v = kTaskFailed;
+        } else {
+            hipError_t e = have_stream ? hipSuccess : hipErrorOutOfMemory;
+            if (e == hipSuccess && t.after) e = hipEventSynchronize(t.after);
+            if (e == hipSuccess && t.n)
+                e = hipMemcpyAsync(t.dst, t.src, t.n,
+                                   t.kind == HostTask::kD2H ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                v = kTaskFailed;
+            } else {
+                s->host_copies++;
+                s->host_copy_bytes += t.n;
+            }
+        }
+        t.flag->store(v, std::memory_order_release);
+        r->tasks.fetch_sub(1, std::memory_order_acq_rel);
+    }
+    if (st) (void)hipStreamDestroy(st);
+}
+
+// Dump slot x % 2 holds no payload still to be copied out of window x.
+bool down_done(const Req* r, const Lane& L, uint64_t x) {
+    if (r->pinned) return hipEventQuery(L.slot_ev[x % 2]) == hipSuccess;
+    return L.fl[kFlDown0 + x % 2].load(std::memory_order_acquire) == x + 1;
+}
+
+// A host task of the request's lane failed.
+bool lane_failed(const Lane& L) {
+    for (int i = 0; i < kLaneFlags; ++i)
+        if (L.fl[i].load(std::memory_order_acquire) == kTaskFailed) return true;
+    return false;
 }
 
 uint32_t* next_ticket_slot(ckpt_server* s) {
@@ -173,7 +318,7 @@ uint32_t* next_ticket_slot(ckpt_server* s) {
 #define SCHK(call)                                   \
     do {                                             \
         hipError_t e_ = (call);                      \
-        if (e_ != hipSuccess) { finish(s, r, CKPT_EHIP); return; } \
+        if (e_ != hipSuccess) { fail_req(s, r, CKPT_EHIP); return; } \
     } while (0)
 
 // ---------------------------------------------------------------- admission
@@ -224,8 +369,18 @@ void admit_dump(ckpt_server* s, Req* r) {
     SCHK(L.staging.ensure(2 * s->slot));
     SCHK(L.ensure_hs(8 * (r->W + 2) + 64));
     SCHK(L.ensure_events(r->W + 1));
-    r->out = image_new(kHeader + r->tl + r->upper);
-    if (!r->out) { finish(s, r, CKPT_ENOMEM); return; }
+    // the image is allocated by a worker (pinning gigabytes takes tens of
+    // milliseconds); the request's first windows may run meanwhile
+    r->alloc_bytes = kHeader + r->tl + r->upper;
+    {
+        HostTask t{};
+        t.kind = HostTask::kAlloc;
+        t.r = r;
+        t.n = r->alloc_bytes;
+        t.flag = &L.fl[kFlAlloc];
+        t.value = 1;
+        host_task(s, t);
+    }
     if (r->rq.prev && pv.n_chunks) {
         // pinned: later windows of this request read it while other requests
         // complete and insert their own tables
@@ -242,7 +397,7 @@ void admit_dump(ckpt_server* s, Req* r) {
     SCHK(launch_chunk_map(L.descs.as<AllocDesc>(), r->n, r->C, L.amap.as<uint32_t>(), s->s_dump));
     SCHK(launch_fill32(L.ctl.as<uint32_t>(), 0, (16 * (r->W + 2) + 64) / 4, s->s_dump));
     SCHK(launch_fill32(L.kinds.as<uint32_t>(), 0, ceil_div(r->tl - 32ull * r->n - 4 * r->nc, 4), s->s_dump));
-    r->phase = kRun;
+    r->phase = kAlloc;
 }
 
 void admit_restore(ckpt_server* s, Req* r) {
@@ -287,8 +442,19 @@ void admit_restore(ckpt_server* s, Req* r) {
     SCHK(L.amap.ensure(4 * std::max<uint64_t>(v.n_chunks, 1)));
     SCHK(hipMemcpyAsync(L.descs.p, r->d.data(), sizeof(AllocDesc) * r->d.size(), hipMemcpyHostToDevice, st));
     SCHK(launch_chunk_map(L.descs.as<AllocDesc>(), (uint32_t)r->d.size(), r->C, L.amap.as<uint32_t>(), st));
-    SCHK(hipMemcpyAsync(L.arc.p, v.recs, len_a, hipMemcpyHostToDevice, st));
-    SCHK(hipMemcpyAsync(L.kinds.p, v.kinds, len_b, hipMemcpyHostToDevice, st));
+    r->pinned = r->rq.img->pinned;
+    if (r->pinned) {
+        SCHK(hipMemcpyAsync(L.arc.p, v.recs, len_a, hipMemcpyHostToDevice, st));
+        SCHK(hipMemcpyAsync(L.kinds.p, v.kinds, len_b, hipMemcpyHostToDevice, st));
+    } else {
+        // tables of a pageable image: host copy into the lane's pinned bounce
+        // buffer (the previous request's uploads from it are done: the lane
+        // was free), then an asynchronous upload
+        SCHK(L.ensure_ht(v.tl));
+        memcpy(L.ht, v.recs, v.tl);
+        SCHK(hipMemcpyAsync(L.arc.p, L.ht, len_a, hipMemcpyHostToDevice, st));
+        SCHK(hipMemcpyAsync(L.kinds.p, L.ht + len_a, len_b, hipMemcpyHostToDevice, st));
+    }
     SCHK(launch_fill32(reinterpret_cast<uint32_t*>(ctl), 0, (64 + 4 * (r->W + 4)) / 4, st));
     SCHK(launch_fill64(reinterpret_cast<uint64_t*>(ctl + 40), ~0ull, 2, st));
     DigestPlan dp;
@@ -330,14 +496,14 @@ void restore_validated(ckpt_server* s, Req* r) {
     const uint32_t* dig = reinterpret_cast<const uint32_t*>(L.hs);
     const uint64_t* cnt = reinterpret_cast<const uint64_t*>(L.hs + 16);
     const uint64_t len_a = 32ull * v.n_allocs + 4 * v.n_chunks, len_b = v.tl - len_a;
-    if (crc_combine(dig[0], dig[1], len_b) != v.tables_crc) { finish(s, r, CKPT_ECORRUPT); return; }
+    if (crc_combine(dig[0], dig[1], len_b) != v.tables_crc) { fail_req(s, r, CKPT_ECORRUPT); return; }
     const uint64_t nz = cnt[0], nd = cnt[1], nu = cnt[2], ninv = cnt[3];
-    if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != v.n_chunks) { finish(s, r, CKPT_ECORRUPT); return; }
+    if (ninv || (nu && !(v.flags & 1u)) || nz + nd + nu != v.n_chunks) { fail_req(s, r, CKPT_ECORRUPT); return; }
     const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
-    if ((v.n_chunks ? wb[r->W] : 0) != v.D) { finish(s, r, CKPT_ECORRUPT); return; }
-    if (v.n_allocs != r->n) { finish(s, r, CKPT_EMISMATCH); return; }
+    if ((v.n_chunks ? wb[r->W] : 0) != v.D) { fail_req(s, r, CKPT_ECORRUPT); return; }
+    if (v.n_allocs != r->n) { fail_req(s, r, CKPT_EMISMATCH); return; }
     for (uint32_t a = 0; a < r->n; ++a)
-        if (r->table[a].id != r->d[a].id || r->table[a].size != r->d[a].size) { finish(s, r, CKPT_EMISMATCH); return; }
+        if (r->table[a].id != r->d[a].id || r->table[a].size != r->d[a].size) { fail_req(s, r, CKPT_EMISMATCH); return; }
     r->nu = nu;
     if (nu) {
         int T, K;
@@ -377,14 +543,20 @@ void launch_merged(ckpt_server* s, bool dump) {
     ckpt_ctx* c = s->ctx;
     std::vector<Req*> batch;
     for (Req* r : s->active) {
-        if (r->phase != kRun || (r->rq.kind == CKPT_REQ_DUMP) != dump || r->launched >= r->W) continue;
+        // a dump's windows may run while its image is being allocated
+        if ((r->phase != kRun && !(dump && r->phase == kAlloc)) || (r->rq.kind == CKPT_REQ_DUMP) != dump ||
+            r->launched >= r->W)
+            continue;
         Lane& L = s->lanes[r->lane];
         const uint64_t w = r->launched;
         if (dump) {
             // at most two windows in flight: slot w%2 must have been copied out
-            if (w >= 2 && (r->copied < w - 1 || hipEventQuery(L.slot_ev[w % 2]) != hipSuccess)) continue;
+            if (w >= 2 && (r->copied < w - 1 || !down_done(r, L, w - 2))) continue;
         } else {
-            if (r->staged <= w || hipEventQuery(L.ev[w]) != hipSuccess) continue;   // payload not up yet
+            if (r->staged <= w) continue;   // payload not up yet
+            if (r->pinned ? hipEventQuery(L.ev[w]) != hipSuccess
+                          : L.fl[kFlUp0 + w % 2].load(std::memory_order_acquire) != w + 1)
+                continue;
         }
         if (r->nc == 0) { r->launched = r->W; continue; }
         batch.push_back(r);
@@ -420,7 +592,7 @@ void launch_merged(ckpt_server* s, bool dump) {
         if (dump) {
             if (L.status.next(st, &j.epoch) != hipSuccess) {
                 // a request whose launch cannot be prepared fails alone
-                finish(s, r, CKPT_EHIP);
+                fail_req(s, r, CKPT_EHIP);
                 continue;
             }
             j.crc_out = reinterpret_cast<uint32_t*>(L.arc.as<uint8_t>() + 32ull * r->n);
@@ -430,7 +602,8 @@ void launch_merged(ckpt_server* s, bool dump) {
             j.wtotal = reinterpret_cast<uint64_t*>(L.ctl.as<uint8_t>()) + w;
             j.err = reinterpret_cast<uint32_t*>(L.ctl.as<uint8_t>() + 16 * (r->W + 2));
             // the slot's previous copy must be finished before it is overwritten
-            if (w >= 2) hipStreamWaitEvent(st, L.slot_ev[w % 2], 0);
+            // (a pageable image's copy is: its flag was seen above)
+            if (w >= 2 && r->pinned) hipStreamWaitEvent(st, L.slot_ev[w % 2], 0);
         } else {
             uint8_t* ctl = L.ctl.as<uint8_t>();
             const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
@@ -440,7 +613,7 @@ void launch_merged(ckpt_server* s, bool dump) {
             j.slot_base = wb[w];
             j.bad = reinterpret_cast<unsigned long long*>(ctl + 40);
             j.err = reinterpret_cast<uint32_t*>(ctl + 56);
-            hipStreamWaitEvent(st, L.ev[w], 0);   // payload copy of this window
+            if (r->pinned) hipStreamWaitEvent(st, L.ev[w], 0);   // payload copy of this window
         }
         jl.prefix[jl.n_jobs] = total;
         total += j.g1 - j.g0;
@@ -466,23 +639,43 @@ void launch_merged(ckpt_server* s, bool dump) {
     s->launches++;
     s->max_batch = std::max<uint64_t>(s->max_batch, used.size());
     if (e != hipSuccess)
-        for (Req* r : used) finish(s, r, CKPT_EHIP);
+        for (Req* r : used) fail_req(s, r, CKPT_EHIP);
 }
 
 // ---------------------------------------------------------------- per-request progress
 void progress_dump(ckpt_server* s, Req* r) {
     ckpt_ctx* c = s->ctx;
     Lane& L = s->lanes[r->lane];
-    // copy out finished windows, in order
+    if (lane_failed(L)) { fail_req(s, r, L.fl[kFlAlloc].load() == kTaskFailed ? CKPT_ENOMEM : CKPT_EHIP); return; }
+    if (r->phase == kAlloc) {
+        if (L.fl[kFlAlloc].load(std::memory_order_acquire) != 1) return;   // image not allocated yet
+        r->pinned = r->out->pinned;
+        r->phase = kRun;
+    }
+    // copy out finished windows, in order: pinned images by the copy engine
+    // on the download stream, pageable ones by a worker
     while (r->copied < r->launched && hipEventQuery(L.ev[r->copied]) == hipSuccess) {
         const uint64_t w = r->copied;
         const uint64_t dw = reinterpret_cast<const uint64_t*>(L.hs)[w];
-        if (dw > s->slot || r->pos + dw > r->upper) { finish(s, r, CKPT_EHIP); return; }
-        SCHK(hipStreamWaitEvent(s->s_down, L.ev[w], 0));
-        if (dw)
-            SCHK(hipMemcpyAsync(r->out->p + kHeader + r->tl + r->pos, L.staging.as<uint8_t>() + (w % 2) * s->slot, dw,
-                                hipMemcpyDeviceToHost, s->s_down));
-        SCHK(hipEventRecord(L.slot_ev[w % 2], s->s_down));
+        if (dw > s->slot || r->pos + dw > r->upper) { fail_req(s, r, CKPT_EHIP); return; }
+        uint8_t* dst = r->out->p + kHeader + r->tl + r->pos;
+        const uint8_t* src = L.staging.as<uint8_t>() + (w % 2) * s->slot;
+        if (r->pinned) {
+            SCHK(hipStreamWaitEvent(s->s_down, L.ev[w], 0));
+            if (dw) SCHK(hipMemcpyAsync(dst, src, dw, hipMemcpyDeviceToHost, s->s_down));
+            SCHK(hipEventRecord(L.slot_ev[w % 2], s->s_down));
+        } else {
+            // the window's kernel is done (its event was seen above)
+            HostTask t{};
+            t.kind = HostTask::kD2H;
+            t.r = r;
+            t.dst = dst;
+            t.src = src;
+            t.n = dw;
+            t.flag = &L.fl[kFlDown0 + w % 2];
+            t.value = w + 1;
+            host_task(s, t);
+        }
         r->pos += dw;
         r->copied++;
     }
@@ -508,8 +701,15 @@ void progress_dump(ckpt_server* s, Req* r) {
         DigestPlan dp;
         SCHK(digest_prepare(c, &L.dig, L.arc.as<uint8_t>(), len_a, L.kinds.as<uint8_t>(), len_b, &dp, s->s_dump));
         SCHK(digest_enqueue(c, dp, hdig, s->s_dump));
-        SCHK(hipMemcpyAsync(r->out->p + kHeader, L.arc.p, len_a, hipMemcpyDeviceToHost, s->s_dump));
-        SCHK(hipMemcpyAsync(r->out->p + kHeader + len_a, L.kinds.p, len_b, hipMemcpyDeviceToHost, s->s_dump));
+        // tables: straight into a pinned image, through the lane's pinned
+        // bounce buffer for a pageable one (moved on the host at the end)
+        uint8_t* tdst = r->out->p + kHeader;
+        if (!r->pinned) {
+            SCHK(L.ensure_ht(r->tl));
+            tdst = L.ht;
+        }
+        SCHK(hipMemcpyAsync(tdst, L.arc.p, len_a, hipMemcpyDeviceToHost, s->s_dump));
+        SCHK(hipMemcpyAsync(tdst + len_a, L.kinds.p, len_b, hipMemcpyDeviceToHost, s->s_dump));
         SCHK(hipMemcpyAsync(hdig + 2, L.ctl.as<uint8_t>() + 16 * (r->W + 2), 4, hipMemcpyDeviceToHost, s->s_dump));
         digest_insert(c, r->out->uid, crc_dev, r->nc, s->s_dump);
         SCHK(hipEventRecord(L.fin, s->s_dump));
@@ -517,12 +717,14 @@ void progress_dump(ckpt_server* s, Req* r) {
         return;
     }
     if (r->phase == kFinal && hipEventQuery(L.fin) == hipSuccess) {
-        if (r->W && hipEventQuery(L.slot_ev[(r->W - 1) % 2]) != hipSuccess) return;
-        if (r->W > 1 && hipEventQuery(L.slot_ev[(r->W - 2) % 2]) != hipSuccess) return;
+        if (r->W && !down_done(r, L, r->W - 1)) return;
+        if (r->W > 1 && !down_done(r, L, r->W - 2)) return;
+        if (r->tasks.load(std::memory_order_acquire) != 0) return;
         const uint32_t* hdig = reinterpret_cast<const uint32_t*>(L.hs + 8 * (r->W + 1));
-        if (hdig[2]) { finish(s, r, CKPT_EHIP); return; }
+        if (hdig[2]) { fail_req(s, r, CKPT_EHIP); return; }
         const uint64_t len_a = 32ull * r->n + 4 * r->nc, len_b = r->tl - len_a;
         uint8_t* h = r->out->p;
+        if (!r->pinned) memcpy(h + kHeader, L.ht, r->tl);
         memcpy(h, "MICKPT01", 8);
         put32(h + 8, 1);
         put32(h + 12, r->rq.prev ? 1u : 0u);
@@ -551,25 +753,40 @@ void progress_restore(ckpt_server* s, Req* r) {
     if (r->phase == kVerify) {
         if (hipEventQuery(L.fin) != hipSuccess) return;
         const uint64_t bad = *reinterpret_cast<const uint64_t*>(L.hs + 64);
-        if (bad != kNoChunk) { finish(s, r, CKPT_EBASE); return; }
+        if (bad != kNoChunk) { fail_req(s, r, CKPT_EBASE); return; }
         r->phase = kRun;
         return;
     }
     if (r->phase == kRun) {
-        // stage payload windows ahead of the kernels: two slots
+        if (lane_failed(L)) { fail_req(s, r, CKPT_EHIP); return; }
+        // stage payload windows ahead of the kernels: two slots; a pinned
+        // image by the copy engine on the upload stream, a pageable one by a
+        // worker (which first waits for the kernel that last read the slot)
         const uint64_t* wb = reinterpret_cast<const uint64_t*>(L.hs + 128);
         while (r->staged < r->W && r->staged < r->launched + 2) {
             const uint64_t w = r->staged;
-            if (w >= 2) {
-                if (r->launched < w - 1) break;
-                SCHK(hipStreamWaitEvent(s->s_up, L.slot_ev[w % 2], 0));   // kernel of window w-2 done
-            }
+            if (w >= 2 && r->launched < w - 1) break;
             const uint64_t len = r->nc ? wb[w + 1] - wb[w] : 0;
-            if (len > s->slot) { finish(s, r, CKPT_ECORRUPT); return; }
-            if (len)
-                SCHK(hipMemcpyAsync(L.staging.as<uint8_t>() + (w % 2) * s->slot, r->v.payload + wb[w], len,
-                                    hipMemcpyHostToDevice, s->s_up));
-            SCHK(hipEventRecord(L.ev[w], s->s_up));
+            if (len > s->slot) { fail_req(s, r, CKPT_ECORRUPT); return; }
+            uint8_t* dst = L.staging.as<uint8_t>() + (w % 2) * s->slot;
+            if (r->pinned) {
+                if (w >= 2) SCHK(hipStreamWaitEvent(s->s_up, L.slot_ev[w % 2], 0));   // kernel of window w-2 done
+                if (len) SCHK(hipMemcpyAsync(dst, r->v.payload + wb[w], len, hipMemcpyHostToDevice, s->s_up));
+                SCHK(hipEventRecord(L.ev[w], s->s_up));
+            } else {
+                // slot_ev[w % 2] was recorded with window w-2's kernel and is
+                // recorded again only with window w's, after this copy
+                HostTask t{};
+                t.kind = HostTask::kH2D;
+                t.r = r;
+                t.dst = dst;
+                t.src = r->v.payload + wb[w];
+                t.n = len;
+                t.after = w >= 2 ? L.slot_ev[w % 2] : nullptr;
+                t.flag = &L.fl[kFlUp0 + w % 2];
+                t.value = w + 1;
+                host_task(s, t);
+            }
             r->staged++;
         }
         if (r->launched == r->W) {
@@ -596,10 +813,10 @@ void progress_restore(ckpt_server* s, Req* r) {
         return;
     }
     if (r->phase == kFinal) {
-        if (hipEventQuery(L.fin) != hipSuccess) return;
+        if (hipEventQuery(L.fin) != hipSuccess || r->tasks.load(std::memory_order_acquire) != 0) return;
         const uint64_t* q = reinterpret_cast<const uint64_t*>(L.hs + 64);
-        if ((uint32_t)q[2]) { finish(s, r, CKPT_EHIP); return; }
-        if (q[0] != kNoChunk || q[1] != kNoChunk) { finish(s, r, CKPT_ECORRUPT); return; }
+        if ((uint32_t)q[2]) { fail_req(s, r, CKPT_EHIP); return; }
+        if (q[0] != kNoChunk || q[1] != kNoChunk) { fail_req(s, r, CKPT_ECORRUPT); return; }
         finish(s, r, CKPT_OK);
     }
 }
@@ -629,6 +846,9 @@ void loop(ckpt_server* s) {
                 if (lane < 0) break;
                 s->pending.pop_front();
                 s->lanes[lane].busy = true;
+                // no task of the lane's previous request is left (it ended
+                // only once its count was 0)
+                for (int i = 0; i < kLaneFlags; ++i) s->lanes[lane].fl[i].store(0, std::memory_order_relaxed);
                 s->reserved += 2 * s->slot;
                 r->lane = lane;
                 r->t_admit = now;
@@ -649,13 +869,14 @@ void loop(ckpt_server* s) {
         }
         for (Req* r : s->active) {
             if (r->phase == kDone) continue;
-            if (r->rq.kind == CKPT_REQ_DUMP) progress_dump(s, r);
+            if (r->phase == kDrain) drain_step(s, r);
+            else if (r->rq.kind == CKPT_REQ_DUMP) progress_dump(s, r);
             else progress_restore(s, r);
         }
         launch_merged(s, true);
         launch_merged(s, false);
         for (Req* r : s->active) {
-            if (r->phase == kDone) continue;
+            if (r->phase == kDone || r->phase == kDrain) continue;
             if (r->rq.kind == CKPT_REQ_DUMP) progress_dump(s, r);
             else progress_restore(s, r);
         }
@@ -694,6 +915,14 @@ extern "C" int ckpt_serve_create(ckpt_ctx* ctx, uint32_t max_active, uint64_t bu
         if (hipStreamCreateWithFlags(p, hipStreamNonBlocking) != hipSuccess) { delete s; return CKPT_EHIP; }
     if (s->tickets.ensure(4 * 1024) != hipSuccess) { delete s; return CKPT_ENOMEM; }
     s->lanes.resize(max_active);
+    s->flags.reset(new std::atomic<uint64_t>[kLaneFlags * max_active]);
+    for (uint32_t i = 0; i < kLaneFlags * max_active; ++i) s->flags[i].store(0);
+    for (uint32_t i = 0; i < max_active; ++i) s->lanes[i].fl = &s->flags[kLaneFlags * i];
+    // host workers for copies that involve pageable images (four reached
+    // ~48 GB/s of pageable copies in either direction, one 17-27 GB/s)
+    int nw = 4;
+    if (const char* env = getenv("MICKPT_SERVE_HOST_THREADS")) nw = std::max(1, std::min(32, atoi(env)));
+    for (int i = 0; i < nw; ++i) s->workers.emplace_back(worker, s);
     s->th = std::thread(loop, s);
     *out = s;
     return CKPT_OK;
@@ -762,6 +991,9 @@ extern "C" int ckpt_serve_stats(ckpt_server* s, ckpt_server_stats* st) {
         st->p99_ns = q(0.99);
         st->mean_wait_ns = s->wait_sum / s->lat.size();
     }
+    st->max_wait_ns = s->max_wait;
+    st->host_copies = s->host_copies.load();
+    st->host_copy_bytes = s->host_copy_bytes.load();
     return CKPT_OK;
 }
 
@@ -773,6 +1005,12 @@ extern "C" void ckpt_serve_destroy(ckpt_server* s) {
     }
     s->cv.notify_all();
     if (s->th.joinable()) s->th.join();
+    {
+        std::lock_guard<std::mutex> g(s->tmu);
+        s->tstop = true;
+    }
+    s->tcv.notify_all();
+    for (std::thread& t : s->workers) t.join();
     hipStream_t ss[] = {s->s_dump, s->s_rest, s->s_up, s->s_down};
     for (hipStream_t x : ss)
         if (x) { hipStreamSynchronize(x); hipStreamDestroy(x); }

@@ -75,7 +75,8 @@ class ckpt_request(ctypes.Structure):
 class ckpt_server_stats(ctypes.Structure):
     _fields_ = [("submitted", _u64), ("completed", _u64), ("failed", _u64), ("bytes_logical", _u64),
                 ("bytes_link", _u64), ("launches", _u64), ("max_batch", _u64), ("p50_ns", _u64),
-                ("p99_ns", _u64), ("mean_wait_ns", _u64)]
+                ("p99_ns", _u64), ("mean_wait_ns", _u64), ("max_wait_ns", _u64), ("host_copies", _u64),
+                ("host_copy_bytes", _u64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -124,3 +124,47 @@ def test_serving_errors_and_deadline(ctx):
         mk.ckpt_serve_destroy(srv)
     assert res["mismatch"][0] == mk.CKPT_EMISMATCH
     assert res["late"][0] == mk.CKPT_ETIMEOUT
+
+
+def test_pageable_images_through_host_workers(ctx):
+    """Every image in pageable host memory (MICKPT_HOST_PAGEABLE): the served
+    loop moves payload windows between the device and those images on its
+    host worker threads (dumps of several windows reuse each staging slot
+    only once the worker has copied it out; restores launch a window only
+    once its payload is up). Images equal the plain path's byte for byte and
+    restores write back the base states."""
+    os.environ["MICKPT_SERVE_WINDOW"] = str(1 << 20)
+    os.environ["MICKPT_HOST_PAGEABLE"] = "1"
+    try:
+        tenants = {k: _tenant_table(40 + k, 4 + k, 20 + 8 * k) for k in range(4)}
+        opts = mk.make_opts(chunk_size=C)
+        base = {k: mk.ckpt_dump(ctx, tab, opts=opts)[1] for k, tab in tenants.items()}
+        for k, tab in tenants.items():
+            workloads.mutate_runs(tab, seed=60 + k, chunk=C, frac=0.2, run_mean=3)
+        alone_full = {k: mk.ckpt_dump(ctx, tab, opts=opts)[1] for k, tab in tenants.items()}
+        alone_delta = {k: mk.ckpt_dump(ctx, tab, prev=base[k], opts=opts)[1] for k, tab in tenants.items()}
+        targets = {k: [(i, torch.full_like(t, 0x44)) for i, t in tab] for k, tab in tenants.items()}
+        srv = mk.ckpt_serve_create(ctx, max_active=6, budget=1 << 30)
+        try:
+            tickets = {}
+            for k, tab in tenants.items():
+                tickets[("full", k)] = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, tab, tenant=k)[1]
+                tickets[("delta", k)] = mk.ckpt_serve_submit(srv, mk.REQ_DUMP, tab, prev=base[k], tenant=k)[1]
+                tickets[("restore", k)] = mk.ckpt_serve_submit(srv, mk.REQ_RESTORE, targets[k], img=base[k],
+                                                               tenant=k)[1]
+            res = _wait(srv, tickets)
+            st = mk.ckpt_serve_stats(srv)
+        finally:
+            mk.ckpt_serve_destroy(srv)
+        assert st.completed == len(tickets) and st.failed == 0 and st.host_copies > 0
+        for k in tenants:
+            for kind, want in (("full", alone_full[k]), ("delta", alone_delta[k])):
+                rc, img, _ = res[(kind, k)]
+                assert rc == 0 and np.array_equal(img.view(), want.view()), (kind, k)
+            assert res[("restore", k)][0] == 0
+        torch.cuda.synchronize()
+        for k in tenants:
+            rc, img, _ = mk.ckpt_dump(ctx, targets[k], opts=opts)
+            assert rc == 0 and np.array_equal(img.view(), base[k].view())
+    finally:
+        del os.environ["MICKPT_HOST_PAGEABLE"]

@@ -181,6 +181,45 @@ def mutate_runs(table, seed=33, chunk=65536, frac=0.05, run_mean=16):
     return int(dirty.sum())
 
 
+def dirty_chunks(table, seed, chunk=65536, frac=0.05, run_mean=16):
+    """Chunks to rewrite, as in mutate_runs (run starts uniform over all
+    chunks, geometric run lengths, until `frac` of the chunks are covered),
+    restricted to full-length chunks: per allocation a device tensor of
+    chunk indices (for apply_dirty)."""
+    rng = np.random.default_rng(seed)
+    counts = [(t.numel() * t.element_size() + chunk - 1) // chunk for _, t in table]
+    starts = np.cumsum([0] + counts)
+    total = int(starts[-1])
+    dirty = np.zeros(total, dtype=bool)
+    target, covered = int(frac * total), 0
+    while covered < target:
+        s = int(rng.integers(0, total))
+        e = min(total, s + _geom(rng, run_mean))
+        covered += int((~dirty[s:e]).sum())
+        dirty[s:e] = True
+    out = []
+    for a, (_, t) in enumerate(table):
+        nfull = (t.numel() * t.element_size()) // chunk
+        idx = np.nonzero(dirty[starts[a]:starts[a] + nfull])[0]
+        out.append(torch.from_numpy(idx.astype(np.int64)).to(t.device))
+    return out
+
+
+def apply_dirty(table, plan, chunk=65536):
+    """Rewrite the planned chunks in place: every byte of each is incremented
+    (mod 256), so each planned chunk changes (a few device operations per
+    allocation, issued on the current stream)."""
+    for (_, t), idx in zip(table, plan):
+        if idx.numel() == 0:
+            continue
+        b = t.view(-1).view(torch.uint8) if t.dtype != torch.uint8 else t.view(-1)
+        nfull = b.numel() // chunk
+        rows = b[:nfull * chunk].view(nfull, chunk)
+        step = max(1, (256 << 20) // chunk)      # bounded temporaries (the gathered rows)
+        for lo in range(0, idx.numel(), step):
+            rows[idx[lo:lo + step]] += 1
+
+
 def fragmented_state(device="cuda", seed=4, total=60 * 10**9, n=10000, zero_block=256 << 10, zero_p=0.3):
     """Allocator-like fragmentation: n allocations, sizes log-uniform in
     [256 B, 256 MiB] rescaled to `total`, random bytes, zero regions as
