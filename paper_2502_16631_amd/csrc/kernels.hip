@@ -497,9 +497,11 @@ k_chunks(JobList jl) {
                 }
                 const uint64_t plen = kd == kData ? len16 : 0;
                 if (tid < 64) {
+                    __builtin_amdgcn_s_setprio(3);   // as in k_dump_stream
                     const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
                                              : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
                     if (tid == 0) s_off = e;
+                    __builtin_amdgcn_s_setprio(0);
                 }
                 lds_barrier();
                 const uint64_t excl = s_off;
@@ -723,9 +725,14 @@ k_dump_stream(JobList jl) {
             }
             const uint64_t plen = kd == kData ? len16 : 0;
             if (tid < 64) {
+                // the look-back wave at the highest priority: the work-group's
+                // other waves wait for its result, while the CU's other
+                // work-group keeps its memory streams going (-2 % kernel time)
+                __builtin_amdgcn_s_setprio(3);
                 const uint64_t e = early ? lb_walk(job.status, g - job.g0, plen, job.epoch, job.err)
                                          : lookback(job.status, g - job.g0, plen, job.epoch, job.err);
                 if (tid == 0) s_off = e;
+                __builtin_amdgcn_s_setprio(0);
             }
             lds_barrier();
             const uint64_t excl = s_off;
