@@ -170,6 +170,20 @@ def _rss_gb():
     return float("nan")
 
 
+def _hip_last_error():
+    """hipGetLastError of the calling thread (and clears it): 0 when no HIP call
+    of this thread has left an error behind."""
+    import ctypes
+    return int(ctypes.CDLL("libamdhip64.so").hipGetLastError())
+
+
+def _dev_gb(torch):
+    """Free device memory and what torch holds, GB."""
+    free, total = torch.cuda.mem_get_info()
+    return "device free %.1f of %.1f GB, torch reserved %.1f GB" % (free / 1e9, total / 1e9,
+                                                                   torch.cuda.memory_reserved() / 1e9)
+
+
 def _tenant_states(torch, n_t, total, seed=5):
     """32 tenant device states, sizes log-uniform in [100 MB, 40 GB] rescaled
     to `total` bytes (the c5 draw), kinds cycling DL-like (bf16 weights
@@ -180,15 +194,17 @@ def _tenant_states(torch, n_t, total, seed=5):
     tenants = []
     for t, size in enumerate(sizes):
         kind = t % 3
-        if kind == 0:
+        if kind == 0:       # per parameter a bf16 weight (2 bytes) and fp32 state (4 bytes): size / 6 of each
             gen = torch.Generator(device="cuda").manual_seed(100 + t)
-            w = torch.empty(size // 4, dtype=torch.bfloat16, device="cuda").normal_(0, 0.02, generator=gen)
-            m = torch.empty(size // 4, dtype=torch.float32, device="cuda").normal_(0, 1e-3, generator=gen)
+            w = torch.empty(size // 6, dtype=torch.bfloat16, device="cuda").normal_(0, 0.02, generator=gen)
+            m = torch.empty(size // 6, dtype=torch.float32, device="cuda").normal_(0, 1e-3, generator=gen)
             table = [(0, w), (1, m)]
-        elif kind == 1:
-            table, _ = workloads.hpc_state("cuda", seed=100 + t, total=size, n=8, chunk=C)
-        else:
-            table = workloads.fragmented_state("cuda", seed=100 + t, total=size, n=16)
+        elif kind == 1:     # allocations as in the HPC image (512 for 40 GB, 1 MiB - 1 GiB)
+            n = max(8, int(round(512 * size / 40e9)))
+            table, _ = workloads.hpc_state("cuda", seed=100 + t, total=size, n=n, chunk=C)
+        else:               # allocations as in the fragmented state (10,000 for 60 GB, 256 B - 256 MiB)
+            n = max(16, int(round(10000 * size / 60e9)))
+            table = workloads.fragmented_state("cuda", seed=100 + t, total=size, n=n)
         # two clustered dirty sets (5 % of chunks, runs of mean 16), used in turn
         plans = [workloads.dirty_chunks(table, seed=1000 * t + k, chunk=C, frac=0.05, run_mean=16) for k in range(2)]
         tenants.append({"table": table, "N": _nbytes(table), "kind": ("DL", "HPC", "fragmented")[kind],
@@ -234,6 +250,7 @@ def serve(args, torch, mk, link):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()     # the generators' temporaries back to the device
     N_all = sum(t["N"] for t in tenants)
+    _log("tenant states: %.1f GB; %s" % (N_all / 1e9, _dev_gb(torch)))
     # the context's own staging (base dumps, the baseline's plain calls): 8 GiB, windows of 2 GiB
     # for the large tenants; the served loop admits against its own 64 GB budget
     ctx = mk.ckpt_ctx_create(0, 8 << 30)
@@ -243,10 +260,13 @@ def serve(args, torch, mk, link):
         rc, img, _ = mk.ckpt_dump(ctx, t["table"], opts=opts)
         assert rc == 0, mk.ckpt_strerror(rc)
         t["last"] = img
-    _log("tenants ready: %.1f GB of state in %d tenants, base images %.1f GB (%.1f s), host RSS %.1f GB"
-         % (N_all / 1e9, n_t, sum(t["last"].nbytes() for t in tenants) / 1e9, time.perf_counter() - t0, _rss_gb()))
+    _log("tenants ready: %.1f GB of state in %d tenants, base images %.1f GB (%.1f s), host RSS %.1f GB; %s"
+         % (N_all / 1e9, n_t, sum(t["last"].nbytes() for t in tenants) / 1e9, time.perf_counter() - t0, _rss_gb(),
+            _dev_gb(torch)))
     arrivals = _trace(args.rate, args.duration, n_t)
     stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    _log("sticky HIP error of this thread after the base dumps: %d" % _hip_last_error())
 
     def mutate(ten):
         with torch.cuda.stream(stream):

@@ -300,6 +300,9 @@ int dump_fixed(ckpt_ctx* c, const ckpt_alloc_table* table, const ckpt_image* pre
                void* stream, ckpt_result* res, const NaCall& na);
 
 void fill_result(ckpt_result* res);   // a fresh report: zeros, no bad chunk
+// A small pinned host buffer; when the driver's pinned limit is reached,
+// cached image buffers of the pinned pool are given back until it succeeds.
+hipError_t pinned_small(void** p, uint64_t n);
 ckpt_image* image_new(uint64_t cap);
 void image_release(ckpt_image* im);   // returns the memory (pool or heap) and deletes im
 void pick_tile(uint32_t C, uint32_t want_t, int* T, int* K);

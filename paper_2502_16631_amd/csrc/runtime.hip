@@ -21,6 +21,7 @@
 //   4. per-allocation CRCs are checked.
 #include <hip/hip_runtime.h>
 #include <string.h>
+#include <sys/mman.h>
 #include <time.h>
 
 #include <algorithm>
@@ -54,12 +55,108 @@ std::atomic<uint64_t> g_uid{1};
 
 // ------------------------------------------------------------ pinned pool
 // Freed image buffers are kept for reuse: pinning tens of GB costs seconds.
+// Image buffers (in use and cached) stay within a budget below the driver's
+// pinned limit per process (64 GiB on the MI355X hosts measured): the HIP
+// runtime pins host memory of its own (a stream's first launches, staging
+// of pageable copies), and with the limit reached even a kernel launch on a
+// new stream fails. Beyond the budget images are pageable.
 struct PinnedPool {
     std::mutex mu;
     std::multimap<uint64_t, void*> free_;   // capacity -> buffer
-    uint64_t cached = 0;
-    static constexpr uint64_t kMaxCached = 64ull << 30;
+    uint64_t cached = 0, live = 0;
+    uint64_t budget = 56ull << 30;          // MICKPT_PINNED_BUDGET overrides (bytes)
+    PinnedPool() {
+        if (const char* env = getenv("MICKPT_PINNED_BUDGET")) budget = strtoull(env, nullptr, 0);
+    }
+    // the largest cached buffer back to the driver (lock held); false if none
+    bool drop_largest() {
+        if (free_.empty()) return false;
+        auto last = std::prev(free_.end());
+        hipHostFree(last->second);
+        cached -= last->first;
+        free_.erase(last);
+        return true;
+    }
     void* get(uint64_t cap, uint64_t* got) {
+        cap = cap ? cap : 1;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_.lower_bound(cap);
+            if (it != free_.end() && it->first <= cap + cap / 4 + (64ull << 20)) {
+                void* p = it->second;
+                *got = it->first;
+                cached -= it->first;
+                live += it->first;
+                free_.erase(it);
+                return p;
+            }
+            // within the budget, cached buffers given back first if needed
+            while (live + cached + cap > budget)
+                if (!drop_largest()) return nullptr;
+            live += cap;   // reserved while the allocation runs
+        }
+        void* p = nullptr;
+        // on a failure (the driver's limit) give cached buffers back, largest
+        // first, until the allocation succeeds or none is left (a handled
+        // failure must not stay behind as the thread's last HIP error: the
+        // caller's next error check would report it)
+        for (;;) {
+            if (hipHostMalloc(&p, cap, hipHostMallocDefault) == hipSuccess) break;
+            (void)hipGetLastError();
+            p = nullptr;
+            std::lock_guard<std::mutex> g(mu);
+            if (!drop_largest()) {
+                live -= cap;
+                return nullptr;
+            }
+        }
+        *got = cap;
+        return p;
+    }
+    // give the largest cached buffer back to the driver; false if none is cached
+    bool trim_one() {
+        std::lock_guard<std::mutex> g(mu);
+        return drop_largest();
+    }
+    void put(void* p, uint64_t cap) {
+        std::lock_guard<std::mutex> g(mu);
+        live -= cap;
+        while (live + cached + cap > budget && drop_largest()) {
+        }
+        if (live + cached + cap > budget) { hipHostFree(p); return; }
+        free_.emplace(cap, p);
+        cached += cap;
+    }
+};
+PinnedPool& pool() {
+    static PinnedPool* p = new PinnedPool();   // never destroyed: buffers may outlive statics
+    return *p;
+}
+
+// Small pinned host buffers (read-backs, bounce buffers): when the driver's
+// pinned limit is reached, cached image buffers are given back until the
+// allocation succeeds.
+hipError_t pinned_small(void** p, uint64_t n) {
+    for (;;) {
+        hipError_t e = hipHostMalloc(p, n ? n : 1, hipHostMallocDefault);
+        if (e == hipSuccess) return e;
+        (void)hipGetLastError();
+        *p = nullptr;
+        if (!pool().trim_one()) return e;
+    }
+}
+
+// Pageable image memory: anonymous mappings asked for transparent huge
+// pages (a first touch costs ~50 ms per GB in 4 KiB pages, and copies into a
+// fresh image pay it), and freed mappings kept for reuse up to kMaxCached
+// bytes, already faulted in.
+struct PageablePool {
+    std::mutex mu;
+    std::multimap<uint64_t, void*> free_;   // capacity -> mapping
+    uint64_t cached = 0;
+    static constexpr uint64_t kMaxCached = 32ull << 30;
+    void* get(uint64_t cap, uint64_t* got) {
+        cap = (std::max<uint64_t>(cap, 1) + (2ull << 20) - 1) & ~((2ull << 20) - 1);
         {
             std::lock_guard<std::mutex> g(mu);
             auto it = free_.lower_bound(cap);
@@ -71,22 +168,9 @@ struct PinnedPool {
                 return p;
             }
         }
-        void* p = nullptr;
-        // pinned memory is limited per process: on a failure give cached
-        // buffers back, largest first, until the allocation succeeds or none
-        // is left (a handled failure must not stay behind as the thread's
-        // last HIP error: the caller's next error check would report it)
-        for (;;) {
-            if (hipHostMalloc(&p, cap ? cap : 1, hipHostMallocDefault) == hipSuccess) break;
-            (void)hipGetLastError();
-            p = nullptr;
-            std::lock_guard<std::mutex> g(mu);
-            if (free_.empty()) return nullptr;
-            auto last = std::prev(free_.end());
-            hipHostFree(last->second);
-            cached -= last->first;
-            free_.erase(last);
-        }
+        void* p = mmap(nullptr, cap, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+        if (p == MAP_FAILED) return nullptr;
+        (void)madvise(p, cap, MADV_HUGEPAGE);   // a hint: without huge pages the mapping still works
         *got = cap;
         return p;
     }
@@ -94,17 +178,17 @@ struct PinnedPool {
         std::lock_guard<std::mutex> g(mu);
         while (cached + cap > kMaxCached && !free_.empty()) {
             auto it = free_.begin();
-            hipHostFree(it->second);
+            munmap(it->second, it->first);
             cached -= it->first;
             free_.erase(it);
         }
-        if (cached + cap > kMaxCached) { hipHostFree(p); return; }
+        if (cached + cap > kMaxCached) { munmap(p, cap); return; }
         free_.emplace(cap, p);
         cached += cap;
     }
 };
-PinnedPool& pool() {
-    static PinnedPool* p = new PinnedPool();   // never destroyed: buffers may outlive statics
+PageablePool& pageable_pool() {
+    static PageablePool* p = new PageablePool();
     return *p;
 }
 
@@ -122,9 +206,8 @@ ckpt_image* mk::image_new(uint64_t cap) {
         // the driver limits pinned memory per process (64 GiB on the MI355X
         // hosts measured): fall back to pageable memory, which the copy
         // engines reach through the runtime's own staging
-        got = (std::max<uint64_t>(cap, 1) + 4095) & ~4095ull;
-        void* q = nullptr;
-        if (posix_memalign(&q, 4096, got) != 0) { delete im; return nullptr; }
+        void* q = pageable_pool().get(cap, &got);
+        if (!q) { delete im; return nullptr; }
         im->p = static_cast<uint8_t*>(q);
         im->pinned = false;
     }
@@ -136,7 +219,7 @@ ckpt_image* mk::image_new(uint64_t cap) {
 void mk::image_release(ckpt_image* im) {
     if (!im) return;
     if (im->pinned) pool().put(im->p, im->cap);
-    else free(im->p);
+    else pageable_pool().put(im->p, im->cap);
     delete im;
 }
 
@@ -311,7 +394,7 @@ hipError_t ensure_hsmall(ckpt_ctx* c, uint64_t n) {
     if (c->hsmall) hipHostFree(c->hsmall);
     c->hsmall = nullptr;
     c->hsmall_cap = 0;
-    hipError_t e = hipHostMalloc((void**)&c->hsmall, n, hipHostMallocDefault);
+    hipError_t e = pinned_small((void**)&c->hsmall, n);
     if (e == hipSuccess) c->hsmall_cap = n;
     return e;
 }
@@ -322,7 +405,7 @@ hipError_t ensure_hpin(ckpt_ctx* c, uint64_t n) {
     if (c->hpin) (void)hipHostFree(c->hpin);
     c->hpin = nullptr;
     c->hpin_cap = 0;
-    hipError_t e = hipHostMalloc((void**)&c->hpin, n, hipHostMallocDefault);
+    hipError_t e = pinned_small((void**)&c->hpin, n);
     if (e == hipSuccess) c->hpin_cap = n;
     return e;
 }
@@ -489,7 +572,7 @@ extern "C" int ckpt_ctx_create(int device, uint64_t staging_budget, ckpt_ctx** o
     if (e == hipSuccess) e = ensure_copy_streams(c, 2);
     if (e == hipSuccess) e = ensure_events(c, 16);
     if (e == hipSuccess) e = ensure_tevents(c, 4 * kCodecPieces);
-    if (e == hipSuccess) e = ensure_hsmall(c, 4096);
+    if (e == hipSuccess) e = ensure_hsmall(c, 256 << 10);   // read-backs of up to ~32k windows
     for (int i = 0; i < 8 && e == hipSuccess; ++i) e = hipEventCreate(&c->sev[i]);
     if (e == hipSuccess) e = na_setup(device);
     c->hconsts = new EngineConsts();

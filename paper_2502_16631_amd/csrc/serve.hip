@@ -47,13 +47,15 @@ namespace {
 
 constexpr uint64_t kDefaultSlot = 256ull << 20;
 
-// Flags a lane's host work reports through (one value each, set by a
-// worker thread with release order once the work is done): the window whose
-// copy out of dump slot 0 / 1 has completed (+1), the window whose payload is
-// in restore slot 0 / 1 (+1), the dump image allocated (1); kTaskFailed on
-// failure. All are cleared when a request is given the lane.
-enum { kFlDown0 = 0, kFlUp0 = 2, kFlAlloc = 4, kLaneFlags = 5 };
+// Flags a lane's host work reports through (stored or counted by a worker
+// thread with release order once the work is done): pieces copied out of
+// dump slot 0 / 1 and into restore slot 0 / 1 for the window the slot holds
+// (counts), the dump image allocated (1), a failed task (kTaskFailed). All
+// are cleared when a request is given the lane. A window's copy is split
+// into pieces of kCopyPiece bytes, so that several workers move one window.
+enum { kFlDown0 = 0, kFlUp0 = 2, kFlAlloc = 4, kFlFail = 5, kLaneFlags = 6 };
 constexpr uint64_t kTaskFailed = ~0ull;
+constexpr uint64_t kCopyPiece = 64ull << 20;
 
 struct Lane {
     DevBuf descs, arc, kinds, ctl, off, wb, staging, dig, prevcrc, amap;
@@ -63,12 +65,14 @@ struct Lane {
     uint8_t* ht = nullptr;   // pinned bounce buffer for the tables of pageable images
     uint64_t ht_cap = 0;
     std::atomic<uint64_t>* fl = nullptr;   // kLaneFlags flags (owned by the server)
+    uint64_t win[4] = {};                   // the window whose pieces fl[0..3] count
+    uint64_t need[4] = {};                  // how many pieces it has
     hipError_t ensure_ht(uint64_t n) {
         if (n <= ht_cap) return hipSuccess;
         if (ht) hipHostFree(ht);
         ht = nullptr;
         ht_cap = 0;
-        hipError_t e = hipHostMalloc((void**)&ht, n, hipHostMallocDefault);
+        hipError_t e = pinned_small((void**)&ht, n);
         if (e == hipSuccess) ht_cap = n;
         return e;
     }
@@ -81,7 +85,7 @@ struct Lane {
         if (hs) hipHostFree(hs);
         hs = nullptr;
         hs_cap = 0;
-        hipError_t e = hipHostMalloc((void**)&hs, n, hipHostMallocDefault);
+        hipError_t e = pinned_small((void**)&hs, n);
         if (e == hipSuccess) hs_cap = n;
         return e;
     }
@@ -150,8 +154,9 @@ struct HostTask {
     const void* src;
     uint64_t n;
     hipEvent_t after;              // device work to wait for first (nullptr: none)
-    std::atomic<uint64_t>* flag;
-    uint64_t value;                // stored to *flag when done
+    std::atomic<uint64_t>* flag;   // copy: raised by one when done; allocation: set to value
+    uint64_t value;
+    std::atomic<uint64_t>* fail;   // copy: set to kTaskFailed on a failure
 };
 
 }  // namespace
@@ -240,11 +245,10 @@ void drain_step(ckpt_server* s, Req* r) {
     finish(s, r, r->drain_rc);
 }
 
-// Queue host work for the workers. The flag is cleared first; the task
-// counts as the request's until the worker is done with it.
+// Queue host work for the workers; the task counts as the request's until
+// the worker is done with it.
 void host_task(ckpt_server* s, HostTask t) {
     t.r->tasks.fetch_add(1, std::memory_order_acq_rel);
-    t.flag->store(0, std::memory_order_relaxed);
     {
         std::lock_guard<std::mutex> g(s->tmu);
         s->tasks.push_back(t);
@@ -253,9 +257,9 @@ void host_task(ckpt_server* s, HostTask t) {
 }
 
 // A worker: takes tasks in order. A copy that involves pageable memory runs
-// synchronously on the worker's own stream; the flag is stored (release)
-// before the request's task count drops, and the worker touches neither
-// after that.
+// synchronously on the worker's own stream; its slot's piece count is
+// raised (release) before the request's task count drops, and the worker
+// touches neither after that. An allocation stores its flag.
 void worker(ckpt_server* s) {
     (void)hipSetDevice(s->ctx->device);
     hipStream_t st = nullptr;
@@ -269,12 +273,11 @@ void worker(ckpt_server* s) {
             t = s->tasks.front();
             s->tasks.pop_front();
         }
-        uint64_t v = t.value;
         Req* r = t.r;
         if (t.kind == HostTask::kAlloc) {
             ckpt_image* im = image_new(t.n);   // the image of a dump
             r->out = im;   // read by the scheduler only after the flag
-            if (!im) v = kTaskFailed;
+            t.flag->store(im ? t.value : kTaskFailed, std::memory_order_release);
         } else {
             hipError_t e = have_stream ? hipSuccess : hipErrorOutOfMemory;
             if (e == hipSuccess && t.after) e = hipEventSynchronize(t.after);
@@ -284,13 +287,13 @@ void worker(ckpt_server* s) {
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
-                v = kTaskFailed;
+                t.fail->store(kTaskFailed, std::memory_order_release);
             } else {
                 s->host_copies++;
                 s->host_copy_bytes += t.n;
             }
+            t.flag->fetch_add(1, std::memory_order_release);
         }
-        t.flag->store(v, std::memory_order_release);
         r->tasks.fetch_sub(1, std::memory_order_acq_rel);
     }
     if (st) (void)hipStreamDestroy(st);
@@ -299,14 +302,43 @@ void worker(ckpt_server* s) {
 // Dump slot x % 2 holds no payload still to be copied out of window x.
 bool down_done(const Req* r, const Lane& L, uint64_t x) {
     if (r->pinned) return hipEventQuery(L.slot_ev[x % 2]) == hipSuccess;
-    return L.fl[kFlDown0 + x % 2].load(std::memory_order_acquire) == x + 1;
+    const int f = kFlDown0 + (int)(x % 2);
+    return L.win[f] == x && L.fl[f].load(std::memory_order_acquire) == L.need[f];
+}
+
+// Restore slot x % 2 holds the payload of window x.
+bool up_done(const Lane& L, uint64_t x) {
+    const int f = kFlUp0 + (int)(x % 2);
+    return L.win[f] == x && L.fl[f].load(std::memory_order_acquire) == L.need[f];
 }
 
 // A host task of the request's lane failed.
 bool lane_failed(const Lane& L) {
-    for (int i = 0; i < kLaneFlags; ++i)
-        if (L.fl[i].load(std::memory_order_acquire) == kTaskFailed) return true;
-    return false;
+    return L.fl[kFlAlloc].load(std::memory_order_acquire) == kTaskFailed ||
+           L.fl[kFlFail].load(std::memory_order_acquire) == kTaskFailed;
+}
+
+// A window's copy between a staging slot and a pageable image, in pieces of
+// kCopyPiece bytes for the workers; slot flag f then counts them.
+void host_copy(ckpt_server* s, Req* r, Lane& L, int f, uint64_t w, HostTask::Kind kind, uint8_t* dst,
+               const uint8_t* src, uint64_t len, hipEvent_t after) {
+    const uint64_t k = ceil_div(len, kCopyPiece);
+    L.win[f] = w;
+    L.need[f] = k;
+    L.fl[f].store(0, std::memory_order_relaxed);   // published to the workers by the queue's lock
+    for (uint64_t i = 0; i < k; ++i) {
+        const uint64_t lo = i * kCopyPiece, n = std::min(kCopyPiece, len - lo);
+        HostTask t{};
+        t.kind = kind;
+        t.r = r;
+        t.dst = dst + lo;
+        t.src = src + lo;
+        t.n = n;
+        t.after = after;
+        t.flag = &L.fl[f];
+        t.fail = &L.fl[kFlFail];
+        host_task(s, t);
+    }
 }
 
 uint32_t* next_ticket_slot(ckpt_server* s) {
@@ -554,9 +586,7 @@ void launch_merged(ckpt_server* s, bool dump) {
             if (w >= 2 && (r->copied < w - 1 || !down_done(r, L, w - 2))) continue;
         } else {
             if (r->staged <= w) continue;   // payload not up yet
-            if (r->pinned ? hipEventQuery(L.ev[w]) != hipSuccess
-                          : L.fl[kFlUp0 + w % 2].load(std::memory_order_acquire) != w + 1)
-                continue;
+            if (r->pinned ? hipEventQuery(L.ev[w]) != hipSuccess : !up_done(L, w)) continue;
         }
         if (r->nc == 0) { r->launched = r->W; continue; }
         batch.push_back(r);
@@ -646,7 +676,10 @@ void launch_merged(ckpt_server* s, bool dump) {
 void progress_dump(ckpt_server* s, Req* r) {
     ckpt_ctx* c = s->ctx;
     Lane& L = s->lanes[r->lane];
-    if (lane_failed(L)) { fail_req(s, r, L.fl[kFlAlloc].load() == kTaskFailed ? CKPT_ENOMEM : CKPT_EHIP); return; }
+    if (lane_failed(L)) {
+        fail_req(s, r, L.fl[kFlAlloc].load(std::memory_order_acquire) == kTaskFailed ? CKPT_ENOMEM : CKPT_EHIP);
+        return;
+    }
     if (r->phase == kAlloc) {
         if (L.fl[kFlAlloc].load(std::memory_order_acquire) != 1) return;   // image not allocated yet
         r->pinned = r->out->pinned;
@@ -666,15 +699,7 @@ void progress_dump(ckpt_server* s, Req* r) {
             SCHK(hipEventRecord(L.slot_ev[w % 2], s->s_down));
         } else {
             // the window's kernel is done (its event was seen above)
-            HostTask t{};
-            t.kind = HostTask::kD2H;
-            t.r = r;
-            t.dst = dst;
-            t.src = src;
-            t.n = dw;
-            t.flag = &L.fl[kFlDown0 + w % 2];
-            t.value = w + 1;
-            host_task(s, t);
+            host_copy(s, r, L, kFlDown0 + (int)(w % 2), w, HostTask::kD2H, dst, src, dw, nullptr);
         }
         r->pos += dw;
         r->copied++;
@@ -776,16 +801,8 @@ void progress_restore(ckpt_server* s, Req* r) {
             } else {
                 // slot_ev[w % 2] was recorded with window w-2's kernel and is
                 // recorded again only with window w's, after this copy
-                HostTask t{};
-                t.kind = HostTask::kH2D;
-                t.r = r;
-                t.dst = dst;
-                t.src = r->v.payload + wb[w];
-                t.n = len;
-                t.after = w >= 2 ? L.slot_ev[w % 2] : nullptr;
-                t.flag = &L.fl[kFlUp0 + w % 2];
-                t.value = w + 1;
-                host_task(s, t);
+                host_copy(s, r, L, kFlUp0 + (int)(w % 2), w, HostTask::kH2D, dst, r->v.payload + wb[w], len,
+                          w >= 2 ? L.slot_ev[w % 2] : nullptr);
             }
             r->staged++;
         }
@@ -849,6 +866,10 @@ void loop(ckpt_server* s) {
                 // no task of the lane's previous request is left (it ended
                 // only once its count was 0)
                 for (int i = 0; i < kLaneFlags; ++i) s->lanes[lane].fl[i].store(0, std::memory_order_relaxed);
+                for (int i = 0; i < 4; ++i) {
+                    s->lanes[lane].win[i] = ~0ull;
+                    s->lanes[lane].need[i] = 0;
+                }
                 s->reserved += 2 * s->slot;
                 r->lane = lane;
                 r->t_admit = now;
@@ -918,9 +939,18 @@ extern "C" int ckpt_serve_create(ckpt_ctx* ctx, uint32_t max_active, uint64_t bu
     s->flags.reset(new std::atomic<uint64_t>[kLaneFlags * max_active]);
     for (uint32_t i = 0; i < kLaneFlags * max_active; ++i) s->flags[i].store(0);
     for (uint32_t i = 0; i < max_active; ++i) s->lanes[i].fl = &s->flags[kLaneFlags * i];
-    // host workers for copies that involve pageable images (four reached
-    // ~48 GB/s of pageable copies in either direction, one 17-27 GB/s)
-    int nw = 4;
+    // each lane's pinned read-back and bounce buffers, made before images
+    // take the pinned memory the driver grants (they grow if a request needs more)
+    for (Lane& L : s->lanes)
+        if (L.ensure_hs(64 << 10) != hipSuccess || L.ensure_ht(8 << 20) != hipSuccess) {
+            for (Lane& x : s->lanes) x.release();
+            delete s;
+            return CKPT_ENOMEM;
+        }
+    // host workers for copies that involve pageable images (one thread made
+    // 17-27 GB/s of pageable copies, four ~48 GB/s together; on the served
+    // configuration twelve workers gave p99 4.2 s against 5.6 s with eight)
+    int nw = 12;
     if (const char* env = getenv("MICKPT_SERVE_HOST_THREADS")) nw = std::max(1, std::min(32, atoi(env)));
     for (int i = 0; i < nw; ++i) s->workers.emplace_back(worker, s);
     s->th = std::thread(loop, s);

@@ -184,8 +184,8 @@ def mutate_runs(table, seed=33, chunk=65536, frac=0.05, run_mean=16):
 def dirty_chunks(table, seed, chunk=65536, frac=0.05, run_mean=16):
     """Chunks to rewrite, as in mutate_runs (run starts uniform over all
     chunks, geometric run lengths, until `frac` of the chunks are covered),
-    restricted to full-length chunks: per allocation a device tensor of
-    chunk indices (for apply_dirty)."""
+    restricted to full-length chunks: per allocation a list of runs
+    (first chunk, end chunk) for apply_dirty."""
     rng = np.random.default_rng(seed)
     counts = [(t.numel() * t.element_size() + chunk - 1) // chunk for _, t in table]
     starts = np.cumsum([0] + counts)
@@ -200,24 +200,22 @@ def dirty_chunks(table, seed, chunk=65536, frac=0.05, run_mean=16):
     out = []
     for a, (_, t) in enumerate(table):
         nfull = (t.numel() * t.element_size()) // chunk
-        idx = np.nonzero(dirty[starts[a]:starts[a] + nfull])[0]
-        out.append(torch.from_numpy(idx.astype(np.int64)).to(t.device))
+        m = np.concatenate([[False], dirty[starts[a]:starts[a] + nfull], [False]]).astype(np.int8)
+        edges = np.flatnonzero(np.diff(m))
+        out.append([(int(lo), int(hi)) for lo, hi in zip(edges[0::2], edges[1::2])])
     return out
 
 
 def apply_dirty(table, plan, chunk=65536):
-    """Rewrite the planned chunks in place: every byte of each is incremented
-    (mod 256), so each planned chunk changes (a few device operations per
-    allocation, issued on the current stream)."""
-    for (_, t), idx in zip(table, plan):
-        if idx.numel() == 0:
+    """Rewrite the planned runs of chunks in place: every byte of each is
+    incremented (mod 256), so each planned chunk changes (one elementwise
+    operation per run, issued on the current stream)."""
+    for (_, t), runs in zip(table, plan):
+        if not runs:
             continue
         b = t.view(-1).view(torch.uint8) if t.dtype != torch.uint8 else t.view(-1)
-        nfull = b.numel() // chunk
-        rows = b[:nfull * chunk].view(nfull, chunk)
-        step = max(1, (256 << 20) // chunk)      # bounded temporaries (the gathered rows)
-        for lo in range(0, idx.numel(), step):
-            rows[idx[lo:lo + step]] += 1
+        for lo, hi in runs:
+            b[lo * chunk:hi * chunk] += 1
 
 
 def fragmented_state(device="cuda", seed=4, total=60 * 10**9, n=10000, zero_block=256 << 10, zero_p=0.3):
