@@ -315,7 +315,10 @@ uint32_t ckpt_crc32c(const void* p, uint64_t n);
  * separate streams so their work overlaps on the device. Each request's
  * result is the same as that of the plain calls (its image is byte-identical
  * to ckpt_dump's with 64 KiB chunks). Tenants' digest tables stay resident
- * in the context for their incremental dumps. */
+ * in the context for their incremental dumps. Copies between the device and
+ * images in pageable host memory (beyond the pinned budget) and the
+ * allocation of dump images run on host worker threads of the server, so
+ * that they never hold up the other requests. */
 typedef struct ckpt_server ckpt_server;
 #define CKPT_REQ_DUMP     1
 #define CKPT_REQ_RESTORE  2
