@@ -270,7 +270,8 @@ def main():
                          "request at a time")
     ap.add_argument("--forms", type=int, default=1,
                     help="plain form: also run the incremental and batched forms (compact, 1 + 3 steps each) and "
-                         "report them under 'forms' (0 = skip)")
+                         "the served form (180 GB, 20 s of arrivals, served and baseline legs) and report them "
+                         "under 'forms' (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (each GPU's allocations form an "

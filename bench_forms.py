@@ -592,16 +592,36 @@ def codec(args, torch, mk, link):
 
 
 def summary(args, torch, mk, link):
-    """Compact results of the incremental and batched forms for the default
-    bench line (one warm-up and three timed steps each); a failure of either
-    is reported in its entry and never stops the other."""
+    """Compact results of the incremental, batched and served forms for the
+    default bench line (one warm-up and three timed steps each; the served
+    form for 20 s of arrivals per leg); a failure of one is reported in its
+    entry and never stops the others."""
     import copy
     a = copy.copy(args)
     a.steps, a.warmup, a.scale = 3, 1, 1.0
+    a.serve_state, a.rate, a.duration = 180e9, 20.0, 20.0
     out = {}
-    for name, fn in (("incremental", incremental), ("batched", batched)):
+    for name, fn in (("incremental", incremental), ("batched", batched), ("serve", None)):
         t0 = time.perf_counter()
         try:
+            if name == "serve":
+                # the served configuration (32 tenants, 180 GB) for 20 s of arrivals, through the
+                # request loop and through per-allocation calls one request at a time
+                legs = {}
+                for leg in ("served", "baseline"):
+                    a.serve_leg = leg
+                    r = serve(a, torch, mk, link)
+                    legs[leg] = {"GBps": r["value"], "requests": r["requests"], "completed_ok": r["completed_ok"],
+                                 "failed": r["failed"], "unfinished_at_stop": r["unfinished_at_stop"],
+                                 "latency": r["latency"], "link_GBps": r["link_GBps"]}
+                    if leg == "served":
+                        legs[leg]["mean_wait_ms"] = r["server"]["mean_wait_ms"]
+                        legs[leg]["max_batch"] = r["server"]["max_batch"]
+                    torch.cuda.synchronize()
+                    torch.cuda.empty_cache()
+                out[name] = {"workload": r["config"]["workload"], **legs}
+                out[name]["wall_s"] = round(time.perf_counter() - t0, 1)
+                continue
             r = fn(a, torch, mk, link)
             if name == "incremental":
                 out[name] = {"workload": r["config"]["workload"], "delta_D_bytes": r["config"]["delta_D_bytes"],
