@@ -119,7 +119,8 @@ def copy_kernel_rate(torch, nbytes=4 << 30, reps=5):
 def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
     """Read + write GB/s of the hand-written 128-bit copy kernel
     (csrc/copyprobe.hip: contiguous tiles per work-group, four or eight
-    blocks in flight per thread), best over a sweep of grid sizes,
+    blocks in flight per thread), best over a sweep of grid sizes (from one
+    work-group per CU up),
     work-group widths, loads in flight and plain / non-temporal stores: the
     measured copy ceiling of this GPU."""
     import ctypes
@@ -132,7 +133,7 @@ def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     best = None
-    for blocks in (1024, 2048, 4096, 8192, 16384):
+    for blocks in (256, 512, 1024, 2048, 4096, 8192, 16384):
         for threads in (256, 512, 1024):
             for nt in (0, 1, 2, 3):
                 ms = ctypes.c_float(0)
