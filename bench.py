@@ -117,12 +117,12 @@ def copy_kernel_rate(torch, nbytes=4 << 30, reps=5):
 
 
 def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
-    """Read + write GB/s of the hand-written 128-bit copy kernel
-    (csrc/copyprobe.hip: contiguous tiles per work-group, four or eight
-    blocks in flight per thread), best over a sweep of grid sizes (from one
-    work-group per CU up),
-    work-group widths, loads in flight and plain / non-temporal stores: the
-    measured copy ceiling of this GPU."""
+    """Read + write GB/s of the hand-written 128-bit copy kernels
+    (csrc/copyprobe.hip: contiguous tiles per work-group with four or eight
+    blocks in flight per thread, or 64 KiB chunks taken by ticket as the
+    dump kernel takes them), best over a sweep of grid sizes (from one
+    work-group per CU up), work-group widths, loads in flight and plain /
+    non-temporal stores: the measured copy ceiling of this GPU."""
     import ctypes
     so = os.path.join(ROOT, "paper_2502_16631_amd", "libmkcopy.so")
     L = ctypes.CDLL(so)
@@ -132,18 +132,19 @@ def copy_kernel_ceiling(torch, nbytes=4 << 30, reps=3):
     src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    shapes = [(blocks, threads, nt) for blocks in (256, 512, 1024, 2048, 4096, 8192, 16384)
+              for threads in (256, 512, 1024) for nt in (0, 1, 2, 3)]
+    shapes += [(blocks, 512, nt) for blocks in (256, 512, 768, 1024) for nt in (4, 5)]
     best = None
-    for blocks in (256, 512, 1024, 2048, 4096, 8192, 16384):
-        for threads in (256, 512, 1024):
-            for nt in (0, 1, 2, 3):
-                ms = ctypes.c_float(0)
-                rc = L.mkcopy_run(dst.data_ptr(), src.data_ptr(), nbytes, blocks, threads, nt, reps, ctypes.byref(ms))
-                if rc != 0:
-                    raise RuntimeError("copy kernel: hip error %d" % rc)
-                gbs = 2.0 * nbytes / (ms.value * 1e-3) / 1e9
-                if best is None or gbs > best["GBps"]:
-                    best = {"GBps": round(gbs, 1), "blocks": blocks, "threads": threads, "nt_stores": bool(nt & 1),
-                            "loads_in_flight": 8 if nt & 2 else 4}
+    for blocks, threads, nt in shapes:
+        ms = ctypes.c_float(0)
+        rc = L.mkcopy_run(dst.data_ptr(), src.data_ptr(), nbytes, blocks, threads, nt, reps, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError("copy kernel: hip error %d" % rc)
+        gbs = 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+        if best is None or gbs > best["GBps"]:
+            best = {"GBps": round(gbs, 1), "pattern": "chunk tickets" if nt & 4 else "tiles", "blocks": blocks,
+                    "threads": threads, "nt_stores": bool(nt & 1), "loads_in_flight": 8 if nt & 6 else 4}
     del src, dst
     torch.cuda.synchronize()
     return best
