@@ -254,15 +254,20 @@ __device__ inline void store_rows_exact(const v4u (&v)[K], uint8_t* base, uint64
     }
 }
 
-// Store whole 16-byte blocks of one pass up to len16 bytes (payload records).
-template <int T, int K>
+// Store whole 16-byte blocks of one pass up to len16 bytes (payload records);
+// NT: as non-temporal stores (the staging window is read next by the copy
+// engines, not by a kernel).
+template <int T, int K, bool NT = false>
 __device__ inline void store_rows_padded(const v4u (&v)[K], uint8_t* base, uint64_t len16, uint32_t tid, bool active) {
     constexpr uint32_t R = 16u * T;
     if (!active) return;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const uint32_t o = r * R + 16u * tid;
-        if (o < len16) gstore(base + o, v[r]);
+        if (o < len16) {
+            if constexpr (NT) __builtin_nontemporal_store(v[r], (gv4*)(base + o));
+            else gstore(base + o, v[r]);
+        }
     }
 }
 
@@ -599,8 +604,15 @@ k_dump_stream(JobList jl) {
     constexpr uint32_t R = 16u * T;       // bytes per row
     constexpr uint32_t C = R * K;         // the chunk is one tile
     constexpr uint32_t BUF = K > 1 ? (K - 1) * R : 16;
-    __shared__ uint32_t s_dt[16 * 256];
-    __shared__ __attribute__((aligned(16))) uint8_t s_buf[BUF];
+    // The tables at the start of LDS: every lookup's table offset then fits
+    // the 16-bit offset field of the LDS read, and a lookup's address takes
+    // one instruction (byte select and scale). The streamed rows follow.
+    __shared__ struct __attribute__((aligned(16))) {
+        uint32_t dt[16 * 256];
+        uint8_t buf[BUF];
+    } s_lds;
+    uint32_t* const s_dt = s_lds.dt;
+    uint8_t* const s_buf = s_lds.buf;
     __shared__ uint32_t s_red[NW];
     __shared__ uint32_t s_any[NW];
     __shared__ uint32_t s_tk[2];
@@ -739,7 +751,7 @@ k_dump_stream(JobList jl) {
             }
             lds_barrier();
             const uint64_t excl = s_off;
-            if (kd == kData) store_rows_padded<T, K>(v, job.slot + excl, len16, ltid, true);
+            if (kd == kData) store_rows_padded<T, K, true>(v, job.slot + excl, len16, ltid, true);
             if (g + 1 == job.g1 && tid == 0) *job.wtotal = excl + plen;
         }
         tk = tk_next;
