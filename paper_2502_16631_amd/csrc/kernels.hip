@@ -456,13 +456,24 @@ k_chunks(JobList jl) {
             }
             const uint8_t* src = job.slot + (job.off[g] - job.slot_base);
             uint32_t acc = 0, padbad = 0;
-            for (uint32_t p = 0; p < P; ++p) {
-                const uint64_t lp = (uint64_t)p * TILE;
+            if (P == 1 && full && T >= 64) {
+                // a whole one-tile chunk (uniform): no per-row bounds or padding
+                constexpr uint32_t R = 16u * NT;
                 v4u v[K];
-                const uint64_t rem = len > lp ? len - lp : 0;
-                load_rows_staged<T, K>(v, src + lp, rem, ltid, active, &padbad);
-                if (rem) store_rows_exact<T, K>(v, aptr + lp, rem, ltid, active);
-                acc = crc_rows<K>(v, acc, s_dt);
+#pragma unroll
+                for (int r = 0; r < K; ++r) v[r] = gload(src + r * R + 16u * ltid);
+#pragma unroll
+                for (int r = 0; r < K; ++r) __builtin_nontemporal_store(v[r], (gv4*)(aptr + r * R + 16u * ltid));
+                acc = crc_rows<K>(v, 0, s_dt);
+            } else {
+                for (uint32_t p = 0; p < P; ++p) {
+                    const uint64_t lp = (uint64_t)p * TILE;
+                    v4u v[K];
+                    const uint64_t rem = len > lp ? len - lp : 0;
+                    load_rows_staged<T, K>(v, src + lp, rem, ltid, active, &padbad);
+                    if (rem) store_rows_exact<T, K>(v, aptr + lp, rem, ltid, active);
+                    acc = crc_rows<K>(v, acc, s_dt);
+                }
             }
             uint32_t raw = wg_xor_lds<NW>(gf_mul_v(acc, lc), s_red);
             const uint32_t pb = wg_any_lds<NW>(padbad != 0, s_any);
