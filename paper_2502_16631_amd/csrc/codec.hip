@@ -112,6 +112,17 @@ __device__ inline void load_bytes(const uint8_t* p, uint32_t* w) {
 
 __device__ inline uint32_t byte_in(const uint32_t* w, int i) { return (w[i >> 2] >> (8 * (i & 3))) & 255u; }
 
+// Entry c (0..14, run-time) of a 16-byte dictionary held in four registers:
+// two byte permutes (v_perm_b32; selector 0x0C gives a zero byte) and a
+// select, where byte_in would need a compare-and-select chain over the four
+// registers.
+__device__ inline uint32_t dict_byte(const uint32_t (&d)[4], uint32_t c) {
+    const uint32_t sel = (c & 7u) | 0x0C0C0C00u;
+    const uint32_t lo = __builtin_amdgcn_perm(d[1], d[0], sel);
+    const uint32_t hi = __builtin_amdgcn_perm(d[3], d[2], sel);
+    return (c & 8u) ? hi : lo;
+}
+
 // Size pass (ENCODE false): the record length of every full DATA chunk; the
 // chunk becomes PACKED when it is shorter than C. Encode pass: the record of
 // every PACKED chunk, written to its payload offset (every byte of the
@@ -488,8 +499,8 @@ __global__ void __launch_bounds__(NT) k_unpack(JobList jl, const uint32_t* rlen,
                     for (int r = 0; r < KH; ++r) {
                         const uint32_t byte = byte_in(cw, r);
                         const uint32_t c0 = byte & 15u, c1 = byte >> 4;
-                        const uint32_t b0 = c0 < 15 ? byte_in(d, c0) : escs[q++];
-                        const uint32_t b1 = c1 < 15 ? byte_in(d, c1) : escs[q++];
+                        const uint32_t b0 = c0 < 15 ? dict_byte(d, c0) : escs[q++];
+                        const uint32_t b1 = c1 < 15 ? dict_byte(d, c1) : escs[q++];
                         out[r][wl] |= b0 << sh;
                         out[r][2 + wl] |= b1 << sh;
                     }
