@@ -186,7 +186,17 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
 #pragma unroll
             for (int r = 0; r < K; ++r)
 #pragma unroll
-                for (int b = 0; b < 16; ++b) atomicAdd(&hist[(b & 7) * 256 + byte_of(v[r], b)], 1u);
+                for (int b = 0; b < 16; ++b) {
+                    // the wave's lanes holding the first lane's value are
+                    // counted with one atomic (the sign / exponent planes
+                    // repeat a few values, and an LDS atomic serializes the
+                    // lanes it finds on one address)
+                    const uint32_t val = byte_of(v[r], b);
+                    const uint32_t v0 = __builtin_amdgcn_readfirstlane(val);
+                    const uint64_t m = __ballot(val == v0);
+                    if (val != v0) atomicAdd(&hist[(b & 7) * 256 + val], 1u);
+                    else if ((tid & 63) == 0) atomicAdd(&hist[(b & 7) * 256 + v0], (uint32_t)__popcll(m));
+                }
             __syncthreads();
             // dictionaries: wave w selects for planes w and w + 4, one value per
             // round (largest count, then smallest value: key = count << 8 | 255 - v)
