@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(NT) k_pack(PackJob j) {
                     const uint32_t v0 = __builtin_amdgcn_readfirstlane(val);
                     const uint64_t m = __ballot(val == v0);
                     if (val != v0) atomicAdd(&hist[(b & 7) * 256 + val], 1u);
-                    else if ((tid & 63) == 0) atomicAdd(&hist[(b & 7) * 256 + v0], (uint32_t)__popcll(m));
+                    else if ((tid & 63) == __ffsll((unsigned long long)m) - 1)   // the lane v0 came from
+                        atomicAdd(&hist[(b & 7) * 256 + v0], (uint32_t)__popcll(m));
                 }
             __syncthreads();
             // dictionaries: wave w selects for planes w and w + 4, one value per
