@@ -1671,6 +1671,15 @@ extern "C" int ckpt_dump_into(ckpt_ctx* c, const ckpt_alloc_table* table, const 
 static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
                        void* stream, ckpt_result* res, bool some, LoadGate* gate);
 
+namespace {
+// A delta's restore launches write only if its base check found no chunk
+// that differs from the base: *gate = (*bad == none). (The chunk kernels'
+// restore mode does nothing when its gate word is 0.)
+__global__ void k_base_gate(uint32_t* gate, const unsigned long long* bad) {
+    if (threadIdx.x == 0) *gate = *bad == ~0ull ? 1u : 0u;
+}
+}  // namespace
+
 int mk::restore_impl(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_table* table, const ckpt_opts* o,
                      void* stream, ckpt_result* res, bool some, LoadGate* gate) {
     const int rc = restore_run(c, img, table, o, stream, res, some, gate);
@@ -1791,10 +1800,15 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
     HIPCHK(ensure_hsmall(c, 8 * (W + 2) + 128));
     HIPCHK(ensure_events(c, std::max<size_t>(2 * W + (size_t)nslots + 2, ncs)));
     const bool timing = !(o && (o->flags & CKPT_OPT_NO_TIMING));
-    if (timing) HIPCHK(ensure_tevents(c, 2 * W));
+    if (timing) HIPCHK(ensure_tevents(c, 2 * W + 2));
     const EngineConsts* ec;
     HIPCHK(get_consts(c, T, C, &ec));
     uint8_t* ctl = c->ctl.as<uint8_t>();
+    // after the window tickets (in the buffer's 64-byte tail): a delta's base
+    // check result and the gate it sets for the restore launches
+    const uint64_t ctl_bas = (ctl_wtk + 4 * (W + 2) + 7) & ~7ull;
+    unsigned long long* bas = reinterpret_cast<unsigned long long*>(ctl + ctl_bas);
+    uint32_t* bgate = reinterpret_cast<uint32_t*>(ctl + ctl_bas + 8);
     uint32_t* ticket = reinterpret_cast<uint32_t*>(ctl);
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctl + ctl_cnt);
     unsigned long long* bad = reinterpret_cast<unsigned long long*>(ctl + ctl_bad);
@@ -2186,8 +2200,20 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
     };
     const uint64_t t_valid = now_ns();
 
-    // 2) a delta needs its base in place
-    if (nu) {
+    // 2) a delta needs its base in place. A plain full restore checks it on
+    // the device while its payload goes up (the check gates the restore
+    // launches, so nothing is written unless it passed, and the result is
+    // read with the others at the end); codec and on-demand restores wait
+    // for the check first.
+    const bool base_overlap = nu && !some && !codec;
+    if (nu && base_overlap) {
+        HIPCHK(launch_fill64(reinterpret_cast<uint64_t*>(bas), ~0ull, 1, c->s_main));
+        if (timing) HIPCHK(hipEventRecord(c->tevents[2 * W], c->s_main));
+        HIPCHK(verify_pass(0, bas));
+        if (timing) HIPCHK(hipEventRecord(c->tevents[2 * W + 1], c->s_main));
+        hipLaunchKernelGGL(k_base_gate, dim3(1), dim3(64), 0, c->s_main, bgate, bas);
+        HIPCHK(hipGetLastError());
+    } else if (nu) {
         HIPCHK(verify_pass(0, bad));
         HIPCHK(hipMemcpyAsync(hq + 4, bad, 8, hipMemcpyDeviceToHost, c->s_main));
         HIPCHK(hipStreamSynchronize(c->s_main));
@@ -2196,6 +2222,7 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
             return CKPT_EBASE;
         }
     }
+    uint32_t* const rgate = base_overlap ? bgate : nullptr;
     const uint64_t t_based = now_ns();
 
     // 3) windows: payload slice up, scatter + verify
@@ -2249,6 +2276,7 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
                 j.slot_base = wbeg[w];
                 j.bad = bad;
                 j.err = err;
+                j.gate = rgate;
                 jl.prefix[jl.n_jobs] = tot;
                 tot += j.g1 - j.g0;
                 jl.n_jobs++;
@@ -2298,6 +2326,7 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
         j.slot_base = wbeg[w];
         j.bad = bad;
         j.err = err;
+        j.gate = rgate;
         int grid;
         HIPCHK(grid_for(c, T, K, kModeRestore, j.g1 - j.g0, &grid));
         if (timing) HIPCHK(hipEventRecord(c->tevents[2 * w], c->s_main));
@@ -2339,6 +2368,14 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
         if (res) res->hip_error = (int32_t)hipErrorLaunchTimeOut;
         return CKPT_EHIP;
     }
+    if (base_overlap) {
+        uint64_t hbas = 0;
+        HIPCHK(hipMemcpy(&hbas, bas, 8, hipMemcpyDeviceToHost));
+        if (hbas != kNoChunk) {   // the restore launches were gated off: nothing was written
+            if (res) res->first_bad_chunk = hbas;
+            return CKPT_EBASE;
+        }
+    }
     if (res) {
         uint64_t moved = 0, logical = 0;
         for (uint64_t w = 0; w < W; ++w) moved += wend[w] - wbeg[w];
@@ -2357,7 +2394,8 @@ static int restore_run(ckpt_ctx* c, const ckpt_image* img, const ckpt_alloc_tabl
         res->ns_kernel = timing ? timed_ns(c, merged ? ceil_div(W, (uint64_t)kMaxJobs) : W) : 0;
         res->ns_total = now_ns() - t_start;
         res->ns_stage[0] = t_valid - t_start;
-        res->ns_stage[1] = nu ? t_based - t_valid : 0;
+        res->ns_stage[1] = !nu ? 0 : (base_overlap && timing) ? span_ns(c->tevents[2 * W], c->tevents[2 * W + 1])
+                                                               : t_based - t_valid;
         res->ns_stage[2] = res->ns_link;
         res->ns_stage[3] = res->ns_kernel;
         if (timing && strict) res->ns_stage[4] = span_ns(c->sev[0], c->sev[1]);

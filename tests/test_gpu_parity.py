@@ -347,6 +347,9 @@ def test_error_paths_match_the_oracle(ctx):
     rc, res = mk.ckpt_restore(ctx, d_img, wrong)
     want = corc.restore(d_or, [(i, np.full(t.numel(), 3, np.uint8)) for i, t in table])
     assert (rc, res.first_bad_chunk) == want and rc == mk.CKPT_EBASE
+    # the base check runs before any chunk is written: the targets are untouched
+    torch.cuda.synchronize()
+    assert all(bool((t == 3).all()) for _, t in wrong)
 
 
 def test_pageable_host_images(ctx):
