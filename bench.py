@@ -314,6 +314,7 @@ def main():
     ref = [(i, t.clone()) for i, t in table] if args.check else None
 
     dump_s, rest_s, kern_ns, kern_launches, rest_kern_ns = [], [], [], [], []
+    dump_st, rest_st = [], []   # ckpt_result.ns_stage of each timed step
     info = {}
 
     def step(timed):
@@ -330,6 +331,8 @@ def main():
             kern_ns.append(res.ns_kernel)
             kern_launches.append(res.windows)
             rest_kern_ns.append(rres.ns_kernel)
+            dump_st.append(list(res.ns_stage))
+            rest_st.append(list(rres.ns_stage))
             info.update(D=res.n_payload, n_chunks=res.n_chunks, windows=res.windows, zero=res.n_zero,
                         link_bytes=res.link_bytes)
         img.free()
@@ -377,6 +380,12 @@ def main():
         "dump_p99_ms": round(pct(dump_s, 99) * 1e3, 3),
         "restore_p50_ms": round(pct(rest_s, 50) * 1e3, 3),
         "restore_p99_ms": round(pct(rest_s, 99) * 1e3, 3),
+        # p50 over the timed steps of each stage (ms): dump set-up, chunk
+        # kernels, -, -, host link, finalize, -, whole call; restore validate,
+        # base check, host link, scatter + verify, strict re-read, finalize, -,
+        # whole call
+        "dump_stage_ms_p50": [round(pct([st[i] for st in dump_st], 50) / 1e6, 3) for i in range(8)],
+        "restore_stage_ms_p50": [round(pct([st[i] for st in rest_st], 50) / 1e6, 3) for i in range(8)],
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
         "dump_frac_of_link": round((info["link_bytes"] / (sum(dump_s) / len(dump_s)) / 1e9) / link["d2h"], 4),
         "restore_frac_of_link": round((info["link_bytes"] / (sum(rest_s) / len(rest_s)) / 1e9) / link["h2d"], 4),

@@ -142,7 +142,9 @@ typedef struct {
      *          [5] finalize (per-allocation combine, table digests, tables copied
      *          out)  [6] unused  [7] whole call, wall time;
      * restore: [0] validate (tables up, digest, offsets scan, host checks), wall
-     *          time  [1] base check of a delta, wall time  [2] host link: first to
+     *          time  [1] base check of a delta (a plain full restore runs it on
+     *          the device beside the upload: its HIP-event time; otherwise the
+     *          host waits for it: wall time)  [2] host link: first to
      *          last payload copy, wall time  [3] scatter + fused verify kernels
      *          (codec decode included)  [4] strict re-read  [5] finalize
      *          (per-allocation check)  [6] unused  [7] whole call, wall time. */

@@ -350,6 +350,19 @@ def test_error_paths_match_the_oracle(ctx):
     # the base check runs before any chunk is written: the targets are untouched
     torch.cuda.synchronize()
     assert all(bool((t == 3).all()) for _, t in wrong)
+    # likewise with the strict re-read, and on the on-demand path (whose
+    # base check the host waits for before the first upload)
+    rc, res = mk.ckpt_restore(ctx, d_img, wrong, opts=mk.make_opts(strict_verify=1))
+    assert (rc, res.first_bad_chunk) == want
+    rc, res = mk.ckpt_restore_some(ctx, d_img, wrong)
+    assert (rc, res.first_bad_chunk) == want
+    torch.cuda.synchronize()
+    assert all(bool((t == 3).all()) for _, t in wrong)
+    # and the same targets holding the base then take the delta
+    good = [(i, t.clone()) for i, t in table]
+    rc, _ = mk.ckpt_restore(ctx, d_img, good)
+    assert rc == 0
+    assert all(torch.equal(g, t) for (_, g), (_, t) in zip(good, new))
 
 
 def test_pageable_host_images(ctx):
