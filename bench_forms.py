@@ -51,6 +51,7 @@ def incremental(args, torch, mk, link):
     dirty = workloads.mutate_runs(table, seed=33, chunk=C, frac=0.05, run_mean=16)
     torch.cuda.synchronize()
     t_delta, t_base, t_apply, kern = [], [], [], []
+    st_delta, st_apply = [], []   # ckpt_result.ns_stage of the timed delta dumps and applies
     D = 0
     for k in range(args.warmup + args.steps):
         t0 = time.perf_counter()
@@ -68,6 +69,8 @@ def incremental(args, torch, mk, link):
             t_base.append(t2 - t1)
             t_apply.append(t3 - t2)
             kern.append(dres.ns_kernel)
+            st_delta.append(list(dres.ns_stage))
+            st_apply.append(list(r2.ns_stage))
             D = dres.n_payload
             info = dres.as_dict()
         delta.free()
@@ -87,6 +90,12 @@ def incremental(args, torch, mk, link):
         "delta_dump_ms_p50": round(_pct(t_delta, 50) * 1e3, 2),
         "base_restore_ms_p50": round(_pct(t_base, 50) * 1e3, 2),
         "delta_apply_ms_p50": round(_pct(t_apply, 50) * 1e3, 2),
+        # medians of ckpt_result.ns_stage (ms): delta dump set-up, digest + kind
+        # passes, offsets scans, gathers, host link, finalize, -, whole call;
+        # delta apply validate, base check, host link, scatter + verify, -,
+        # finalize, -, whole call
+        "delta_dump_stage_ms_p50": [round(_pct([x[i] for x in st_delta], 50) / 1e6, 3) for i in range(8)],
+        "delta_apply_stage_ms_p50": [round(_pct([x[i] for x in st_apply], 50) / 1e6, 3) for i in range(8)],
         "delta_link_GBps": round(info["link_bytes"] / td / 1e9, 2),
         "link_measured_GBps": {k: round(v, 2) for k, v in link.items()},
         "roofline": {"bound": "hbm", "achieved": round(alg / k_avg / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
@@ -629,6 +638,8 @@ def summary(args, torch, mk, link):
                              "delta_link_frac": round(r["delta_link_GBps"] / link["d2h"], 4),
                              "base_restore_ms_p50": r["base_restore_ms_p50"],
                              "delta_apply_ms_p50": r["delta_apply_ms_p50"],
+                             "delta_dump_stage_ms_p50": r["delta_dump_stage_ms_p50"],
+                             "delta_apply_stage_ms_p50": r["delta_apply_stage_ms_p50"],
                              "dump_stage_hbm_frac": r["roofline"]["frac"]}
             else:
                 out[name] = {"workload": r["config"]["workload"], "chunk": r["config"]["chunk"],
