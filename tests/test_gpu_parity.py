@@ -52,6 +52,13 @@ def check_parity(ctx, table, c, prev_gpu=None, prev_oracle=None, **kw):
     if not np.array_equal(got, oimg):
         diff = np.nonzero(got != oimg)[0]
         raise AssertionError("image differs at %d bytes, first at %d" % (diff.size, diff[0]))
+    # the reported kind counts are those of the oracle's kind table
+    # (plain layout: header, AllocRec[n], crc[n_c], kind[n_c])
+    _, hdr = corc.parse(oimg)
+    n, nc = hdr["n_allocs"], hdr["n_chunks"]
+    kinds = oimg[64 + 32 * n + 4 * nc:64 + 32 * n + 5 * nc]
+    want = tuple(int((kinds == k).sum()) for k in (ZERO, DATA, UNCHANGED, 3))
+    assert (res.n_zero, res.n_data, res.n_unchanged, res.n_packed) == want
     return img, oimg, res
 
 
