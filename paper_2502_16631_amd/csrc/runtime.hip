@@ -710,16 +710,29 @@ void mk::digest_unpin(ckpt_ctx* c, uint64_t uid) {
 void mk::digest_insert(ckpt_ctx* c, uint64_t uid, const uint32_t* crc_dev, uint64_t nc, hipStream_t s) {
     if (!nc) return;
     if (c->digests.count(uid)) return;   // an image is dumped once; its table never changes
+    // An evicted table's buffer takes the new table when it is large enough:
+    // freeing device memory waits for all work on the device, which in the
+    // served loop would stall every request in flight. Buffers are sized in
+    // powers of two, so that more of them fit a later table. (No launch still
+    // reads a victim: tables read by requests in flight are pinned, and a
+    // plain dump has finished before its call returns.)
+    DevBuf spare;
     if (c->digests.size() >= c->digest_capacity) {
-        // tables pinned by requests in flight are never freed; with every
+        // tables pinned by requests in flight are never evicted; with every
         // entry pinned the new table is not kept
         const uint64_t victim = digest_victim(c->digests, 0);
         if (!victim) return;
-        c->digests[victim].crc.release();
+        spare = c->digests[victim].crc;
         c->digests.erase(victim);
     }
+    uint64_t want = 256;
+    while (want < 4 * nc) want <<= 1;
     DigestEntry& de = c->digests[uid];
-    if (de.crc.ensure(4 * nc) == hipSuccess &&
+    if (spare.p && spare.cap >= 4 * nc)
+        de.crc = spare;
+    else
+        spare.release();
+    if (de.crc.ensure(de.crc.p ? 4 * nc : want) == hipSuccess &&
         hipMemcpyAsync(de.crc.p, crc_dev, 4 * nc, hipMemcpyDeviceToDevice, s) == hipSuccess) {
         de.n_chunks = nc;
         de.last_use = ++c->use_clock;

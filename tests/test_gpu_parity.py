@@ -317,6 +317,31 @@ def test_delta_dump_merge_and_in_place_restore(ctx):
         assert torch.equal(a, b)
 
 
+def test_resident_digest_tables_past_capacity(ctx):
+    """More images than the context keeps digest tables for (8): evicted
+    tables' buffers take later tables of other sizes; deltas against the
+    newest images (tables resident) and the oldest (evicted) match the
+    oracle, and the newest delta restores in place."""
+    c = 4096
+    rng = np.random.default_rng(41)
+    gen = torch.Generator(device=DEV).manual_seed(41)
+    states = []
+    for k in range(11):
+        table = _rand_table(rng, gen, 2 + k % 4, c, zero_p=0.2, max_chunks=2 + 3 * (k % 3))
+        img, oimg, _ = check_parity(ctx, table, c)
+        states.append((table, img, oimg))
+    for k in (0, 1, 9, 10):
+        table, img, oimg = states[k]
+        new = [(i, t.clone()) for i, t in table]
+        workloads.mutate_runs(new, seed=50 + k, chunk=c, frac=0.3, run_mean=2)
+        d_img, _, _ = check_parity(ctx, new, c, prev_gpu=img, prev_oracle=oimg)
+    targets = [(i, t.clone()) for i, t in table]
+    rc, _ = mk.ckpt_restore(ctx, d_img, targets)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for (_, a), (_, b) in zip(targets, new))
+
+
 def test_error_paths_match_the_oracle(ctx):
     c = 4096
     rng = np.random.default_rng(24)
