@@ -237,3 +237,14 @@ def test_pinned_digest_tables_are_never_evicted():
         else:
             i = int(np.nonzero(uids == v)[0][0])
             assert pins[i] == 0 and last[i] == last[free].min()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it exits with status 2 and
+    says why, before touching any device."""
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and "--gpus 2" in p.stderr
+    assert p.stdout == ""
